@@ -1,0 +1,164 @@
+/*
+ * trsyl.h -- robust solver for the triangular Sylvester equation on AMD Instinct MI355X (gfx950)
+ *
+ *     A Y + Y B = alpha C,     A (m x m), B (n x n) upper quasi-triangular (real Schur form),
+ *
+ * after Schwarz & Kjelgaard Mikkelsen, "Robust Task-Parallel Solution of the Triangular
+ * Sylvester Equation" (arXiv 1905.10574).  The scale alpha in (0, 1] is chosen on the fly so
+ * that no intermediate value exceeds the overflow threshold OMEGA = 2^1022 (Sec. 2, eq. (7)).
+ *
+ * Conventions shared by every entry point
+ *   - All matrix pointers are DEVICE pointers to column-major float64 storage with leading
+ *     dimensions (LAPACK layout).  Only the entries of A and B on or above the first
+ *     subdiagonal are read.  A nonzero first-subdiagonal entry T(i+1, i) marks a 2x2 diagonal
+ *     block (Sec. 1, eq. (4)); two consecutive nonzero subdiagonal entries are an error.
+ *   - The caller owns every buffer, including the workspace; the library never allocates
+ *     device memory on the solve path.  Size the workspace with the matching *_workspace_size
+ *     call, for the same arguments and options.
+ *   - Work is enqueued on `stream` and is asynchronous.  Results (Y, the scale exponent, the
+ *     status) are written to device memory in stream order.
+ *   - alpha is returned as an exact power of two: alpha = 2^-e with integer e >= 0 written to
+ *     *scale_log2 (int64), and as a double in *scale (0.0 once e exceeds 1074).  Exponents,
+ *     not doubles, carry the scale because strongly growing problems need e far beyond the
+ *     double range.
+ *   - Return value (synchronous, host): 0 when the work was enqueued, -i when argument i is
+ *     invalid (null pointer, negative size, leading dimension too small, workspace too small,
+ *     bad option), -100 on a HIP launch error.
+ *   - Device status (*info, int32, written in stream order):
+ *        0  success
+ *        1  a pivot of a small 1x1/2x2 Sylvester solve fell below smin and was replaced by
+ *           +-smin (lambda_A + lambda_B = 0 to working precision; Sec. 1 uniqueness
+ *           condition); the result solves a nearby problem
+ *        2  A or B is not upper quasi-triangular (two consecutive nonzero subdiagonals)
+ *        3  non-finite input, or an input entry above OMEGA (precondition of Alg. 2/4)
+ *        4  the persistent scheduler's watchdog expired (a dependency never resolved)
+ *     On status 2 or 3 the contents of C are unspecified.
+ *   - Functions are reentrant: concurrent calls need distinct workspaces.
+ */
+#ifndef TRSYL_H
+#define TRSYL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *trsyl_stream_t; /* a hipStream_t; NULL = the null stream */
+
+enum trsyl_precision {
+    TRSYL_FP64 = 0,        /* every step in FP64 */
+    TRSYL_FP32_REFINE = 1, /* tile updates on FP32 MFMA with power-of-two operand scaling,
+                              tile solves / bounds / residual in FP64, iterative refinement */
+};
+
+enum trsyl_scheduler {
+    TRSYL_SCHED_DAG = 0,    /* one persistent kernel walks the tile dependency graph */
+    TRSYL_SCHED_FRONTS = 1, /* one launch per anti-diagonal front (stream ordered) */
+};
+
+typedef struct trsyl_opts {
+    int32_t tile_m;      /* tile size for A (rows of Y); 0 = default 128.  Range [16, 512] */
+    int32_t tile_n;      /* tile size for B (columns of Y); 0 = tile_m */
+    int32_t precision;   /* enum trsyl_precision */
+    int32_t scheduler;   /* enum trsyl_scheduler */
+    int32_t slabs;       /* row slabs per tile update task; 0 = default (tile rows / 64) */
+    int32_t max_sweeps;  /* refinement sweeps for TRSYL_FP32_REFINE; 0 = default 3 */
+    double refine_tol;   /* eq. (9) target for TRSYL_FP32_REFINE; 0 = default 1e-13 */
+    int32_t workers;     /* persistent workgroups; 0 = one per compute unit */
+    int32_t flags;       /* bit 0: force the robust (non-speculative) tile solve */
+} trsyl_opts;
+
+/* Fill *opts with the defaults. */
+void trsyl_default_opts(trsyl_opts *opts);
+
+/* Workspace bytes needed by trsyl_robust for an m x n problem with these options. */
+size_t trsyl_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts);
+
+/*
+ * Robust solve of A Y + Y B = alpha C (Algorithm 4, Sec. 2.2): tiles of Y carry their own
+ * power-of-two scales; tile solves follow RobustSyl (Algorithm 2), tile updates RobustUpdate
+ * (Algorithm 3); the tiles are rescaled consistently to alpha = min alpha_kl at the end.
+ *   m, n            orders of A and B (>= 0)
+ *   A, lda          device, m x m, lda >= max(1, m), read only
+ *   B, ldb          device, n x n, ldb >= max(1, n), read only
+ *   C, ldc          device, m x n, ldc >= max(1, m); in: C, out: Y (||Y_kl||_inf <= OMEGA)
+ *   scale_log2      device int64[1]: e with alpha = 2^-e
+ *   scale           device double[1]: alpha (0.0 when e > 1074); may be NULL
+ *   info            device int32[1]: status, see above
+ *   opts            host; NULL = defaults
+ *   workspace       device, ws_bytes >= trsyl_workspace_size(m, n, opts), 256-byte aligned
+ */
+int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                 const trsyl_opts *opts, void *workspace, size_t ws_bytes, trsyl_stream_t stream);
+
+/*
+ * Adjoint solve A^T G + G B^T = alpha W, used for gradients (L = <W, Y> gives dL/dC = alpha_Y G,
+ * dL/dA = -G Y^T on A's pattern, dL/dB = -Y^T G).  Same arguments as trsyl_robust with W in C.
+ * The transposed problem is mapped onto the forward one by order reversal:
+ * P A^T P and Q B^T Q are upper quasi-triangular (P, Q reverse the index order), and
+ * G = P Gh Q with (P A^T P) Gh + Gh (Q B^T Q) = alpha P W Q.
+ */
+size_t trsyl_adjoint_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts);
+int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, const double *B,
+                         int64_t ldb, double *W, int64_t ldw, int64_t *scale_log2, double *scale,
+                         int32_t *info, const trsyl_opts *opts, void *workspace, size_t ws_bytes,
+                         trsyl_stream_t stream);
+
+/*
+ * Gradient products for L = <W, Y> with Y the scaled forward output (A Y + Y B = alpha_Y C,
+ * alpha_Y = 2^-eY held fixed), given the adjoint output G with A^T G + G B^T = 2^-eG W:
+ * with Gt = 2^eG G (the unscaled adjoint solution),
+ *   dC = alpha_Y Gt,   dA = -Gt Y^T on A's quasi-triangular pattern,
+ *   dB = -Y^T Gt on B's pattern (upper triangle plus the subdiagonal entries of 2x2 blocks).
+ * eY and eG are read from device memory.  dA (ld ldda), dB (ld lddb), dC (ld lddc) are device
+ * outputs and must not alias the inputs.  Needs no workspace.
+ */
+int trsyl_grad(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+               const double *Y, int64_t ldy, const int64_t *eY, const double *G, int64_t ldg,
+               const int64_t *eG, double *dA, int64_t ldda, double *dB, int64_t lddb, double *dC,
+               int64_t lddc, trsyl_stream_t stream);
+
+/*
+ * Batched robust solve: `count` independent problems of arbitrary sizes in one persistent
+ * launch.  Pointer arrays live in device memory; m, n, lda, ldb, ldc are host arrays.
+ * scale_log2, scale, info are device arrays of length count.  The return value is the host
+ * argument check only; per-problem status goes to info[i].
+ */
+size_t trsyl_batched_workspace_size(int32_t count, const int64_t *m, const int64_t *n,
+                                    const trsyl_opts *opts);
+int trsyl_robust_batched(int32_t count, const int64_t *m, const int64_t *n,
+                         const double *const *A, const int64_t *lda, const double *const *B,
+                         const int64_t *ldb, double *const *C, const int64_t *ldc,
+                         int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
+                         void *workspace, size_t ws_bytes, trsyl_stream_t stream);
+
+/*
+ * Relative residual of eq. (9), evaluated on the device in FP64 with power-of-two
+ * normalisation:  ||alpha C - (A Y + Y B)||_F / ((||A||_F + ||B||_F) ||Y||_F + ||alpha C||_F),
+ * alpha = 2^-e read from device memory.  Writes the quotient to *out (device double).
+ * workspace >= trsyl_residual_workspace_size(m, n).
+ */
+size_t trsyl_residual_workspace_size(int64_t m, int64_t n);
+int trsyl_residual(int64_t m, int64_t n, const double *A, int64_t lda, const double *B,
+                   int64_t ldb, const double *Y, int64_t ldy, const int64_t *e, const double *C,
+                   int64_t ldc, double *out, void *workspace, size_t ws_bytes,
+                   trsyl_stream_t stream);
+
+/*
+ * Diagnostics: evaluate the device versions of ProtectUpdate / ProtectDivision (Sec. 2.1) on
+ * `count` argument triples/pairs.  in: device double[3*count] (c, a, y) or double[2*count]
+ * (b, t); out: device int32[count] exponents s (zeta = 2^-s).
+ */
+int trsyl_debug_protect_update(int32_t count, const double *in, int32_t *out, trsyl_stream_t stream);
+int trsyl_debug_protect_division(int32_t count, const double *in, int32_t *out, trsyl_stream_t stream);
+
+/* Library version string. */
+const char *trsyl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRSYL_H */

@@ -1,0 +1,347 @@
+// C ABI of the robust triangular Sylvester solver (include/trsyl.h): argument checks,
+// workspace layout, the static task order of the persistent scheduler, and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <tuple>
+#include <vector>
+
+#include "../../include/trsyl.h"
+#include "launch.hpp"
+#include "plan.hpp"
+
+using namespace trsyl;
+
+namespace {
+
+constexpr int kDefaultTile = 128;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Resolved {
+    int tm, tn, slabs, precision, scheduler, max_sweeps, workers, flags;
+    double refine_tol;
+};
+
+int device_cus()
+{
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    cache[dev] = cus;
+    return cus;
+}
+
+// Returns 0 or the (negative) index of the offending option argument.
+int resolve(const trsyl_opts *o, Resolved *r, int argpos)
+{
+    trsyl_opts d;
+    trsyl_default_opts(&d);
+    if (!o) o = &d;
+    r->tm = o->tile_m ? o->tile_m : kDefaultTile;
+    r->tn = o->tile_n ? o->tile_n : r->tm;
+    if (r->tm < 16 || r->tm > 256 || r->tn < 16 || r->tn > 256) return -argpos;
+    r->slabs = o->slabs ? o->slabs : std::max(1, (r->tm + 63) / 64);
+    const int rbmax = (r->tm + 1 + 15) / 16;
+    if (r->slabs < 1 || r->slabs > 32 || (rbmax + r->slabs - 1) / r->slabs > kMaxSlabRB) return -argpos;
+    r->precision = o->precision;
+    if (r->precision != TRSYL_FP64 && r->precision != TRSYL_FP32_REFINE) return -argpos;
+    r->scheduler = o->scheduler;
+    if (r->scheduler != TRSYL_SCHED_DAG && r->scheduler != TRSYL_SCHED_FRONTS) return -argpos;
+    r->max_sweeps = o->max_sweeps ? o->max_sweeps : 3;
+    r->refine_tol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
+    r->workers = o->workers > 0 ? o->workers : 0;
+    r->flags = o->flags;
+    return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Workspace layout
+// ------------------------------------------------------------------------------------------
+struct Layout {
+    int pt, qt, workers;
+    int64_t ntasks;
+    size_t rowoff, coloff, anorm, bnorm, bdiag1, tnorm, texp, ver, misc, tasks, scratch, total;
+    size_t zero_begin, zero_end;   // region cleared at the start of each call
+};
+
+int64_t count_tasks(int pt, int qt, int slabs)
+{
+    const int64_t upd = (int64_t)qt * pt * (pt - 1) / 2 + (int64_t)pt * qt * (qt - 1) / 2;
+    return (int64_t)pt * qt + upd * slabs;
+}
+
+Layout make_layout(int64_t m, int64_t n, const Resolved &r)
+{
+    Layout L{};
+    L.pt = (int)((m + r.tm - 1) / r.tm);
+    L.qt = (int)((n + r.tn - 1) / r.tn);
+    const int front = std::min(L.pt, L.qt);
+    L.workers = r.workers ? r.workers : device_cus();
+    L.workers = std::max(L.workers, front);
+    L.ntasks = (r.scheduler == TRSYL_SCHED_DAG) ? count_tasks(L.pt, L.qt, r.slabs) : 0;
+    const size_t nt = (size_t)L.pt * L.qt;
+    size_t o = 0;
+    L.rowoff = o; o = align_up(o + 4 * (size_t)(L.pt + 1));
+    L.coloff = o; o = align_up(o + 4 * (size_t)(L.qt + 1));
+    L.anorm = o; o = align_up(o + 8 * (size_t)L.pt * L.pt);
+    L.bnorm = o; o = align_up(o + 8 * (size_t)L.qt * L.qt);
+    L.bdiag1 = o; o = align_up(o + 8 * (size_t)L.qt);
+    L.tnorm = o; o = align_up(o + 8 * 2 * nt * (size_t)r.slabs);
+    L.texp = o; o = align_up(o + 4 * 2 * nt);
+    L.zero_begin = o;
+    L.ver = o; o = align_up(o + 4 * nt);
+    L.misc = o; o = align_up(o + 64);
+    L.zero_end = o;
+    L.tasks = o; o = align_up(o + 8 * (size_t)L.ntasks);
+    L.scratch = o; o = align_up(o + 8 * (size_t)L.workers * kMaxTile * kMaxTile);
+    L.total = o;
+    return L;
+}
+
+// ------------------------------------------------------------------------------------------
+// Static task order for the persistent scheduler.  A list-scheduling simulation on `workers`
+// identical workers (tasks on the earliest anti-diagonal front first, the tile solve before
+// updates of its front) yields the start order, which is a topological order of the task
+// graph: a solve after all updates of its tile, an update after its source's solve and after
+// the target's previous update (each target takes its updates in the fixed order of
+// update_index()).
+// ------------------------------------------------------------------------------------------
+struct TaskCache {
+    std::vector<uint64_t> tasks;
+    uint64_t *pinned = nullptr;
+};
+
+std::vector<uint64_t> build_tasks(int pt, int qt, int slabs, int workers, double solve_cost)
+{
+    const int nt = pt * qt;
+    std::vector<std::vector<int>> src(nt);
+    std::vector<int> U(nt);
+    for (int T = 0; T < nt; ++T) {
+        const int i = T / qt, l = T % qt;
+        U[T] = (pt - 1 - i) + l;
+        src[T].assign(U[T], -1);
+        for (int ks = i + 1; ks < pt; ++ks) src[T][update_index(pt, i, l, ks, l)] = ks * qt + l;
+        for (int ls = 0; ls < l; ++ls) src[T][update_index(pt, i, l, i, ls)] = i * qt + ls;
+    }
+    std::vector<int> next_u(nt, 0), slabs_left(nt, 0);
+    std::vector<char> busy(nt, 0), solved(nt, 0);
+    // ready queue keyed by (front of the tile written, solve first, sequence)
+    typedef std::tuple<int, int, int64_t, uint64_t> Ready;
+    std::priority_queue<Ready, std::vector<Ready>, std::greater<Ready>> ready;
+    typedef std::tuple<double, int64_t, uint64_t> Event;
+    std::priority_queue<Event, std::vector<Event>, std::greater<Event>> events;
+    int64_t seq = 0;
+    auto front = [&](int T) { return (pt - 1 - T / qt) + T % qt; };
+    auto push_solve = [&](int T) { ready.emplace(front(T), 0, seq++, make_task(kTaskSolve, 0, T, 0, 0)); };
+    auto try_start = [&](int T) {
+        if (busy[T] || next_u[T] >= U[T]) return;
+        const int S = src[T][next_u[T]];
+        if (!solved[S]) return;
+        busy[T] = 1;
+        slabs_left[T] = slabs;
+        const int kind = (S % qt == T % qt) ? kTaskColUpdate : kTaskRowUpdate;
+        for (int s = 0; s < slabs; ++s) ready.emplace(front(T), 1, seq++, make_task(kind, s, T, S, next_u[T]));
+    };
+    for (int T = 0; T < nt; ++T)
+        if (U[T] == 0) push_solve(T);
+    std::vector<uint64_t> order;
+    order.reserve((size_t)count_tasks(pt, qt, slabs));
+    const double ts = solve_cost, tu = 1.0 / slabs;
+    int free_w = workers;
+    double now = 0.0;
+    for (;;) {
+        while (free_w > 0 && !ready.empty()) {
+            const uint64_t task = std::get<3>(ready.top());
+            ready.pop();
+            order.push_back(task);
+            --free_w;
+            events.emplace(now + (task_kind(task) == kTaskSolve ? ts : tu), seq++, task);
+        }
+        if (events.empty()) break;
+        const Event ev = events.top();
+        events.pop();
+        now = std::get<0>(ev);
+        const uint64_t task = std::get<2>(ev);
+        ++free_w;
+        const int T = task_T(task);
+        if (task_kind(task) == kTaskSolve) {
+            solved[T] = 1;
+            const int k = T / qt, l = T % qt;
+            for (int i = 0; i < k; ++i) try_start(i * qt + l);
+            for (int j = l + 1; j < qt; ++j) try_start(k * qt + j);
+        } else if (--slabs_left[T] == 0) {
+            busy[T] = 0;
+            if (++next_u[T] == U[T]) push_solve(T);
+            else try_start(T);
+        }
+    }
+    return order;
+}
+
+const TaskCache *get_tasks(int pt, int qt, int slabs, int workers)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, TaskCache *> cache;
+    std::lock_guard<std::mutex> g(mu);
+    const auto key = std::make_tuple(pt, qt, slabs, workers);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    TaskCache *tc = new TaskCache;
+    tc->tasks = build_tasks(pt, qt, slabs, workers, 4.0);
+    // the kernel trusts the list: exactly count_tasks entries, every tile index in range
+    if ((int64_t)tc->tasks.size() != count_tasks(pt, qt, slabs)) {
+        delete tc;
+        return nullptr;
+    }
+    for (const uint64_t t : tc->tasks) {
+        if (task_T(t) >= pt * qt || task_S(t) >= pt * qt || task_slab(t) >= slabs) {
+            delete tc;
+            return nullptr;
+        }
+    }
+    const size_t bytes = tc->tasks.size() * sizeof(uint64_t);
+    if (hipHostMalloc((void **)&tc->pinned, bytes ? bytes : 8, hipHostMallocDefault) != hipSuccess) {
+        delete tc;
+        return nullptr;
+    }
+    if (bytes) std::memcpy(tc->pinned, tc->tasks.data(), bytes);
+    cache[key] = tc;
+    return tc;
+}
+
+Plan make_plan(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+               double *C, int64_t ldc, const Resolved &r, const Layout &L, char *ws)
+{
+    Plan P{};
+    P.m = m; P.n = n; P.lda = lda; P.ldb = ldb; P.ldc = ldc;
+    P.A = A; P.B = B; P.C = C;
+    P.pt = L.pt; P.qt = L.qt; P.tm = r.tm; P.tn = r.tn; P.slabs = r.slabs; P.flags = r.flags;
+    P.rowoff = (int32_t *)(ws + L.rowoff);
+    P.coloff = (int32_t *)(ws + L.coloff);
+    P.anorm = (double *)(ws + L.anorm);
+    P.bnorm = (double *)(ws + L.bnorm);
+    P.bdiag1 = (double *)(ws + L.bdiag1);
+    P.tnorm = (double *)(ws + L.tnorm);
+    P.texp = (int32_t *)(ws + L.texp);
+    P.ver = (uint32_t *)(ws + L.ver);
+    char *misc = ws + L.misc;
+    P.gmax = (double *)(misc + 0);
+    P.status = (int32_t *)(misc + 8);
+    P.ticket = (uint32_t *)(misc + 12);
+    P.stats = (uint32_t *)(misc + 16);
+    P.tasks = (const uint64_t *)(ws + L.tasks);
+    P.ntasks = (int)L.ntasks;
+    P.scratch = (double *)(ws + L.scratch);
+    P.spin_limit = 100ull * 1000 * 1000 * 10;   // 10 s of the 100 MHz wall clock
+    return P;
+}
+
+bool bad_ptr(const void *p) { return p == nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+void trsyl_default_opts(trsyl_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tile_m = kDefaultTile;
+    o->tile_n = kDefaultTile;
+    o->precision = TRSYL_FP64;
+    o->scheduler = TRSYL_SCHED_DAG;
+    o->max_sweeps = 3;
+    o->refine_tol = 1e-13;
+}
+
+const char *trsyl_version(void) { return "trsyl-mi355x 0.1"; }
+
+size_t trsyl_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts)
+{
+    Resolved r;
+    if (m < 0 || n < 0 || resolve(opts, &r, 3)) return 0;
+    if (m == 0 || n == 0) return kAlign;
+    return make_layout(m, n, r).total;
+}
+
+int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                 const trsyl_opts *opts, void *workspace, size_t ws_bytes, trsyl_stream_t stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && bad_ptr(A)) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (n > 0 && bad_ptr(B)) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (m > 0 && n > 0 && bad_ptr(C)) return -7;
+    if (ldc < std::max<int64_t>(1, m)) return -8;
+    if (bad_ptr(scale_log2)) return -9;
+    if (bad_ptr(info)) return -11;
+    Resolved r;
+    if (int e = resolve(opts, &r, 12)) return e;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -13;
+    const size_t need = trsyl_workspace_size(m, n, opts);
+    if (ws_bytes < need) return -14;
+    if (r.precision != TRSYL_FP64) return -12;   // the refinement driver lives in refine.cpp
+
+    Layout L = make_layout(std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), r);
+    char *ws = (char *)workspace;
+    Plan P = make_plan(m, n, A, lda, B, ldb, C, ldc, r, L, ws);
+    P.e_out = scale_log2;
+    P.scale_out = scale;
+    P.info_out = info;
+    if (m == 0 || n == 0) {
+        P.pt = P.qt = 0;
+        if (launch_fill_zero(ws, kAlign, stream) != hipSuccess) return -100;
+        // finalize with no tiles writes e = 0, alpha = 1 and the (zero) status
+        P.status = (int32_t *)(ws + 8);
+        return launch_finalize(P, stream) == hipSuccess ? 0 : -100;
+    }
+    if (launch_fill_zero(ws + L.zero_begin, L.zero_end - L.zero_begin, stream) != hipSuccess) return -100;
+    if (launch_setup(P, stream) != hipSuccess) return -100;
+    if (r.scheduler == TRSYL_SCHED_DAG) {
+        const TaskCache *tc = get_tasks(L.pt, L.qt, r.slabs, L.workers);
+        if (!tc) return -100;
+        if (hipMemcpyAsync(ws + L.tasks, tc->pinned, tc->tasks.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            return -100;
+        if (launch_dag(P, L.workers, stream) != hipSuccess) return -100;
+    } else {
+        if (launch_fronts(P, stream) != hipSuccess) return -100;
+    }
+    if (launch_finalize(P, stream) != hipSuccess) return -100;
+    return 0;
+}
+
+int trsyl_debug_protect_update(int32_t count, const double *in, int32_t *out, trsyl_stream_t s)
+{
+    if (count < 0) return -1;
+    if (count > 0 && (bad_ptr(in) || bad_ptr(out))) return -2;
+    return launch_debug_protect(0, count, in, out, (hipStream_t)s) == hipSuccess ? 0 : -100;
+}
+
+int trsyl_debug_protect_division(int32_t count, const double *in, int32_t *out, trsyl_stream_t s)
+{
+    if (count < 0) return -1;
+    if (count > 0 && (bad_ptr(in) || bad_ptr(out))) return -2;
+    return launch_debug_protect(1, count, in, out, (hipStream_t)s) == hipSuccess ? 0 : -100;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+"""GPU parity tests of the forward robust solve (C ABI through the ctypes binding) against the
+CPU oracle.
+
+Gates (from the method's contract and the solve's error analysis):
+  * well-separated spectra: e == 0 on both sides and ||Y_gpu - Y_orc||_F / ||Y_orc||_F <= 1e-10;
+  * every case: all entries finite and <= Omega, eq. (9) residual <= 1e-13;
+  * growth inputs: e > 0, and the normalised solutions agree to within a bound derived from the
+    oracle's own spread between two valid tile orders (these inputs are ill-conditioned enough
+    that rounding order alone moves the forward solution; see the oracle tests).
+"""
+import math
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import trsyl_workloads as W
+
+pytestmark = pytest.mark.gpu
+OMEGA = 2.0 ** 1022
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_10574_amd as T
+    T.lib()
+    return T
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb else np.linalg.norm(a)
+
+
+def normalised(Y):
+    mx = np.abs(Y).max()
+    if mx == 0:
+        return Y.copy(), 0
+    e = math.frexp(mx)[1]
+    return np.ldexp(Y, -e), e
+
+
+def gpu_solve(T, A, B, C, **kw):
+    print(f"  gpu solve m={A.shape[0]} n={B.shape[0]} {kw}", flush=True)
+    Y, e, info = T.solve(A, B, C, **kw)
+    return Y.cpu().numpy(), e, info
+
+
+def test_device_primitives_contract(T):
+    rng = np.random.default_rng(7)
+    vals = [0.0, 2.0 ** -1074, 2.0 ** -1022, 0.5, 1.0, 3.0, 1e200, 2.0 ** 1021, 2.0 ** 1022] + \
+        [float(x) for x in 2.0 ** rng.uniform(-1074, 1022, 25)]
+    trip = [(c, a, y) for c in vals[::2] for a in vals for y in vals[::3]]
+    out = T.debug_protect_update(trip)
+    omega = Fraction(2) ** 1022
+    for (c, a, y), s in zip(trip, out):
+        g = Fraction(c) + Fraction(a) * Fraction(y)
+        assert s >= 0 and Fraction(1, 2 ** s) * g <= omega, (c, a, y, s)
+        if s > 1:   # at most one above the minimum (documented guard band)
+            assert Fraction(1, 2 ** (s - 2)) * g > omega
+    ts = [2.0 ** -1074, 1e-300, 0.3, 0.999, 1.0, 7.0]
+    pairs = [(sb * b, st * t) for b in vals for t in ts for sb in (1, -1) for st in (1, -1)]
+    out = T.debug_protect_division(pairs)
+    for (b, t), s in zip(pairs, out):
+        lhs = Fraction(1, 2 ** s) * abs(Fraction(b))
+        assert lhs <= abs(Fraction(t)) * omega
+        if s > 0:
+            assert 2 * lhs > abs(Fraction(t)) * omega
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_workload_vs_oracle(T, orc, seed):
+    A, B, C = W.config_small(seed)
+    Yo, eo, rco = orc.drsylv(A, B, C, 64)
+    for sched in ("dag", "fronts"):
+        Y, e, info = gpu_solve(T, A, B, C, tile=64, scheduler=sched)
+        assert info == 0 and e == 0 and eo == 0
+        assert rel(Y, Yo) <= 1e-10
+        assert orc.relres(A, B, Y, e, C) <= 1e-13
+
+
+SHAPES = [(1, 1), (1, 40), (37, 1), (17, 5), (100, 130), (257, 300), (300, 257), (513, 260)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+@pytest.mark.parametrize("tile", [16, 64, 128])
+def test_ragged_shapes_vs_oracle(T, orc, m, n, tile):
+    A, B, C = W.separated_problem(1000 + m + 7 * n, m, n, p2x2=0.25, upper_scale="sqrt")
+    Yo, eo, _ = orc.drsylv(A, B, C, 32)
+    for sched in ("dag", "fronts"):
+        Y, e, info = gpu_solve(T, A, B, C, tile=tile, scheduler=sched)
+        assert info == 0 and e == 0
+        assert rel(Y, Yo) <= 1e-10, (sched, rel(Y, Yo))
+    assert orc.relres(A, B, Y, e, C) <= 1e-13
+
+
+def test_forced_robust_tile_solve_matches(T, orc):
+    """flags bit 0 skips the speculative tile solve: Algorithm 2 on every tile."""
+    A, B, C = W.separated_problem(5, 200, 170, p2x2=0.3)
+    Yo, eo, _ = orc.drsylv(A, B, C, 64)
+    Y, e, info = gpu_solve(T, A, B, C, tile=64, flags=1)
+    assert info == 0 and e == 0 and rel(Y, Yo) <= 1e-10
+
+
+def _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2):
+    assert np.isfinite(Y).all() and np.abs(Y).max() <= OMEGA and e > 0
+    assert orc.relres(A, B, Y, e, C) <= 1e-13
+    ng, sg = normalised(Y)
+    no, so = normalised(Yo)
+    n2, s2 = normalised(Yo2)
+    assert abs((sg + e) - (so + eo)) <= 1
+    spread = rel(np.ldexp(n2, (s2 + eo2) - (so + eo)), no)
+    err = rel(np.ldexp(ng, (sg + e) - (so + eo)), no)
+    print(f"    growth: e_gpu={e} e_orc={eo} err={err:.2e} oracle spread={spread:.2e}")
+    assert err <= max(1e-8, 100 * spread)
+
+
+@pytest.mark.parametrize("size,tile", [(64, 16), (200, 64), (256, 64)])
+def test_growth_vs_oracle(T, orc, size, tile):
+    A, B, C = W.config_growth(3, size, size)
+    Yo, eo, _ = orc.drsylv(A, B, C, tile)
+    Yo2, eo2, _ = orc.drsylv(A, B, C, max(8, tile // 2))
+    for sched in ("dag", "fronts"):
+        Y, e, info = gpu_solve(T, A, B, C, tile=tile, scheduler=sched)
+        assert info == 0
+        _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2)
+
+
+def test_growth_closed_form(T):
+    """Unscaled substitution overflows; Y/alpha must equal the closed form of
+    (A + nu I) y = 1 with A = mu I + strict upper ones (exact rational reference)."""
+    m, mu = 160, 1e-3
+    nus = [0.0, 2e-4, 5e-4, 1e-4]
+    A = np.triu(np.ones((m, m)), 1) + mu * np.eye(m)
+    B = np.diag(np.array(nus))
+    C = np.ones((m, len(nus)))
+    Y, e, info = gpu_solve(T, A, B, C, tile=48)
+    assert info == 0 and e > 500 and np.isfinite(Y).all() and np.abs(Y).max() <= OMEGA
+    for j, nu in enumerate(nus):
+        d = Fraction(mu + nu)
+        exact = [(1 - 1 / d) ** (m - 1 - i) / d for i in range(m)]
+        got = [Fraction(float(Y[i, j])) * Fraction(2) ** e for i in range(m)]
+        num = sum((g - x) ** 2 for g, x in zip(got, exact))
+        den = sum(x ** 2 for x in exact)
+        assert float(num / den) <= 1e-24
+
+
+def test_status_codes(T):
+    A, B, C = W.config_small(0)
+    bad = C.copy()
+    bad[5, 7] = np.nan
+    _, _, info = gpu_solve(T, A, B, bad, tile=32)
+    assert info == 3
+    big = C.copy()
+    big[0, 0] = 2.0 ** 1023
+    _, _, info = gpu_solve(T, A, B, big, tile=32)
+    assert info == 3
+    A3 = np.triu(np.ones((40, 40)))
+    A3[11, 10] = A3[12, 11] = 1.0
+    _, _, info = gpu_solve(T, A3, np.eye(3), np.ones((40, 3)), tile=16)
+    assert info == 2
+    # lambda_A + lambda_B = 0 for one pair: pivot perturbed, info 1
+    _, _, info = gpu_solve(T, np.array([[1.0, 2.0], [0.0, 3.0]]), np.array([[-3.0]]), np.ones((2, 1)), tile=16)
+    assert info == 1
+
+
+def test_empty(T):
+    import torch
+    Y, e, info = T.solve(np.zeros((0, 0)), np.eye(3), np.zeros((0, 3)))
+    assert e == 0 and info == 0 and tuple(Y.shape) == (0, 3)
