@@ -59,7 +59,7 @@ enum trsyl_scheduler {
 };
 
 typedef struct trsyl_opts {
-    int32_t tile_m;      /* tile size for A (rows of Y); 0 = default 128.  Range [16, 512] */
+    int32_t tile_m;      /* tile size for A (rows of Y); 0 = default 128.  Range [16, 256] */
     int32_t tile_n;      /* tile size for B (columns of Y); 0 = tile_m */
     int32_t precision;   /* enum trsyl_precision */
     int32_t scheduler;   /* enum trsyl_scheduler */
@@ -68,6 +68,12 @@ typedef struct trsyl_opts {
     double refine_tol;   /* eq. (9) target for TRSYL_FP32_REFINE; 0 = default 1e-13 */
     int32_t workers;     /* persistent workgroups; 0 = one per compute unit */
     int32_t flags;       /* bit 0: force the robust (non-speculative) tile solve */
+    void *profile_events; /* optional host pointer to two caller-owned hipEvent_t: the library
+                             records [0] right before and [1] right after the tile-DAG kernel(s)
+                             on `stream`, so their elapsed time is the scheduler's duration */
+    uint64_t *trace;      /* optional device buffer of 4 * (number of tasks) uint64: for task t
+                             of the persistent scheduler, [4t] = task word, [4t+1] = start and
+                             [4t+2] = end (100 MHz wall clock), [4t+3] = workgroup */
 } trsyl_opts;
 
 /* Fill *opts with the defaults. */

@@ -30,7 +30,8 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("scheduler", ctypes.c_int32),
                 ("slabs", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("workers", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("profile_events", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p)]
 
 
 _lib = None

@@ -307,6 +307,7 @@ int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const doubl
     P.e_out = scale_log2;
     P.scale_out = scale;
     P.info_out = info;
+    P.trace = opts ? opts->trace : nullptr;
     if (m == 0 || n == 0) {
         P.pt = P.qt = 0;
         if (launch_fill_zero(ws, kAlign, stream) != hipSuccess) return -100;
@@ -316,16 +317,20 @@ int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const doubl
     }
     if (launch_fill_zero(ws + L.zero_begin, L.zero_end - L.zero_begin, stream) != hipSuccess) return -100;
     if (launch_setup(P, stream) != hipSuccess) return -100;
+    hipEvent_t *ev = opts ? (hipEvent_t *)opts->profile_events : nullptr;
     if (r.scheduler == TRSYL_SCHED_DAG) {
         const TaskCache *tc = get_tasks(L.pt, L.qt, r.slabs, L.workers);
         if (!tc) return -100;
         if (hipMemcpyAsync(ws + L.tasks, tc->pinned, tc->tasks.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return -100;
+        if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
         if (launch_dag(P, L.workers, stream) != hipSuccess) return -100;
     } else {
+        if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
         if (launch_fronts(P, stream) != hipSuccess) return -100;
     }
+    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
     if (launch_finalize(P, stream) != hipSuccess) return -100;
     return 0;
 }

@@ -63,6 +63,7 @@ struct Plan {
     double *scale_out;
     int32_t *info_out;
     uint64_t spin_limit;    // watchdog for dependency waits
+    uint64_t *trace;        // optional per-task timing records (4 words per task)
 };
 
 // A copy of the plan whose every field is read with readfirstlane.  The plan reaches kernels and
@@ -94,6 +95,7 @@ __device__ __forceinline__ Plan uniform_plan(const Plan &in)
     P.scratch = uniptr(in.scratch);
     P.e_out = uniptr(in.e_out); P.scale_out = uniptr(in.scale_out); P.info_out = uniptr(in.info_out);
     P.spin_limit = (uint64_t)uni64((int64_t)in.spin_limit);
+    P.trace = uniptr(in.trace);
     return P;
 }
 

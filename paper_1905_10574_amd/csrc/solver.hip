@@ -193,9 +193,17 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
             if (!ok) set_status(P.status, kWatchdog);
         }
         __syncthreads();
+        const uint64_t tstart = wall_clock64();
         if (uniform(s_ok)) {
             if (kind == kTaskSolve) run_solve(P, T, scratch, L.sol);
             else run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd);
+        }
+        if (P.trace && threadIdx.x == 0) {
+            uint64_t *rec = P.trace + 4 * (size_t)t;
+            rec[0] = task;
+            rec[1] = tstart;
+            rec[2] = wall_clock64();
+            rec[3] = blockIdx.x;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
