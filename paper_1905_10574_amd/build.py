@@ -26,7 +26,10 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, defines: tuple = ()) -> str:
+    """Compile every source and link libtrsyl.so.  `defines` adds -D options (e.g. the optional
+    TRSYL_PHASE_STAMPS timing hooks)."""
+    extra = [f"-D{d}" for d in defines]
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
@@ -35,7 +38,7 @@ def build(verbose: bool = True) -> str:
         if not os.path.exists(path):
             continue
         obj = os.path.join(bdir, src + ".o")
-        _run(["hipcc", "-c", path, "-o", obj] + COMMON + DEVICE)
+        _run(["hipcc", "-c", path, "-o", obj] + COMMON + DEVICE + extra)
         objs.append(obj)
     for src in HOST_SOURCES:
         path = os.path.join(CSRC, src)
@@ -51,5 +54,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(defines=tuple(a[2:] for a in sys.argv[1:] if a.startswith("-D")))
     sys.exit(0)

@@ -54,9 +54,9 @@ int resolve(const trsyl_opts *o, Resolved *r, int argpos)
     r->tm = o->tile_m ? o->tile_m : kDefaultTile;
     r->tn = o->tile_n ? o->tile_n : r->tm;
     if (r->tm < 16 || r->tm > 256 || r->tn < 16 || r->tn > 256) return -argpos;
-    r->slabs = o->slabs ? o->slabs : std::max(1, (r->tm + 63) / 64);
+    r->slabs = o->slabs ? o->slabs : 1;
     const int rbmax = (r->tm + 1 + 15) / 16;
-    if (r->slabs < 1 || r->slabs > 32 || (rbmax + r->slabs - 1) / r->slabs > kMaxSlabRB) return -argpos;
+    if (r->slabs < 1 || r->slabs > 32 || r->slabs > rbmax) return -argpos;
     r->precision = o->precision;
     if (r->precision != TRSYL_FP64 && r->precision != TRSYL_FP32_REFINE) return -argpos;
     r->scheduler = o->scheduler;

@@ -264,6 +264,74 @@ __device__ __forceinline__ void set_status(int32_t *status, int32_t code)
 // Within a chunk of 16 k values, MFMA step j uses k = 4 (l >> 4) + j for the lane's quad, so
 // each lane reads 4 consecutive k of a column of Bop.
 // --------------------------------------------------------------------------------------------
+// Global-memory access helpers.  The solver's pointers come from the plan, so the compiler
+// cannot infer their address space and would emit flat accesses (which also count against the
+// LDS counter and force full waits); ldg / stg cast to the global address space.
+//
+// Data that workgroups of one launch hand to each other (tiles of Y, per-tile norms and
+// exponents) goes through DevView: raw buffer loads and stores whose cache policy asks for device
+// scope (sc1).  Such loads bypass the XCD-private caches' possibly stale copies and such stores
+// write through, so a producer's stores are visible to any consumer once they have completed
+// (s_waitcnt) and the consumer has observed the producer's counter.  No cache-wide invalidation or
+// write-back is needed, so read-only operands (A, B) stay cached.  These are plain (non-atomic)
+// memory operations, so the compiler keeps many in flight; relaxed atomic loads would each be
+// preceded by a full wait.  A view covers `bytes` bytes from a wave-uniform base (offsets are
+// 32-bit); accesses past the end read zero and are dropped, by the buffer range check.
+#ifndef TRSYL_AS_GLOBAL
+#define TRSYL_AS_GLOBAL __attribute__((address_space(1)))
+#endif
+typedef TRSYL_AS_GLOBAL double gdouble;
+
+__device__ __forceinline__ double ldg(const double *p) { return *(const gdouble *)p; }
+__device__ __forceinline__ void stg(double *p, double v) { *(gdouble *)p = v; }
+
+constexpr int kPolicyDevice = 16;        // cache policy bits: sc1 (device scope)
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer descriptor word 3 for gfx9-family parts
+
+struct DevView {
+    __amdgpu_buffer_rsrc_t r;
+};
+// The descriptor must live in scalar registers; its fields are read with readfirstlane so that
+// the compiler sees them as uniform (a view's base and size are the same in every lane).
+__device__ __forceinline__ DevView dev_view(const void *base, uint64_t bytes)
+{
+    const uint64_t b = (uint64_t)(uintptr_t)base;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    void *ub = (void *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    const uint32_t nb = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes));
+    return DevView{__builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)nb, kRsrcWord3)};
+}
+// View of a column-major rows x cols block with leading dimension ld.
+__device__ __forceinline__ DevView dev_view(const double *base, int64_t ld, int rows, int cols)
+{
+    const int64_t n = rows > 0 && cols > 0 ? (int64_t)(cols - 1) * ld + rows : 1;
+    return dev_view((const void *)base, (uint64_t)n * 8u);
+}
+__device__ __forceinline__ double ld_dev(const DevView &v, int64_t idx)
+{
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(v.r, (int)(uint32_t)(idx * 8), 0, kPolicyDevice);
+    double d;
+    __builtin_memcpy(&d, &x, 8);
+    return d;
+}
+__device__ __forceinline__ void st_dev(const DevView &v, int64_t idx, double d)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 x;
+    __builtin_memcpy(&x, &d, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(x, v.r, (int)(uint32_t)(idx * 8), 0, kPolicyDevice);
+}
+__device__ __forceinline__ int32_t ld_dev_i32(const DevView &v, int64_t idx)
+{
+    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(v.r, (int)(uint32_t)(idx * 4), 0, kPolicyDevice);
+}
+__device__ __forceinline__ void st_dev_i32(const DevView &v, int64_t idx, int32_t x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)x, v.r, (int)(uint32_t)(idx * 4), 0, kPolicyDevice);
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c)

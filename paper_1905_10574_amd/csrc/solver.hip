@@ -130,10 +130,9 @@ __global__ void __launch_bounds__(kThreads) k_bounds_C(Plan P)
     if (bad) set_status(P.status, kBadInput);
     best = wg_max(best, red);
     if (threadIdx.x == 0) {
-        double *ns = tile_norm_slot(P, T, 0);
-        ns[0] = best;
-        for (int s = 1; s < P.slabs; ++s) ns[s] = 0.0;
-        *tile_exp_slot(P, T, 0) = 0;
+        tile_norm_store(P, T, 0, 0, best);
+        for (int s = 1; s < P.slabs; ++s) tile_norm_store(P, T, 0, s, 0.0);
+        tile_exp_store(P, T, 0, 0);
         P.ver[T] = 0;
     }
 }
@@ -151,7 +150,7 @@ __device__ __forceinline__ bool wait_count(const Plan &P, const uint32_t *ctr, u
 {
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
         if (wall_clock64() - t0 > P.spin_limit) return false;
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(20);   // ~0.5 us between polls keeps the counters' channels free
     }
     return true;
 }
@@ -186,7 +185,6 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
                 ok = wait_count(P, &P.ver[S], (uint32_t)(tile_updates(P, S) + 1) * slabs, t0) &&
                      wait_count(P, &P.ver[T], (uint32_t)u * slabs, t0);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok ? 1 : 0;
             // on a timeout the task is skipped, but its counter still moves so that every
             // other workgroup drains as well; the status reports the failure
@@ -196,7 +194,14 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
         const uint64_t tstart = wall_clock64();
         if (uniform(s_ok)) {
             if (kind == kTaskSolve) run_solve(P, T, scratch, L.sol);
-            else run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd);
+            else {
+#ifdef TRSYL_PHASE_STAMPS
+                uint64_t *us = P.trace ? P.trace + 4 * (size_t)P.ntasks + 80 * (size_t)P.pt * P.qt + 8 * (size_t)t : nullptr;
+#else
+                uint64_t *us = nullptr;
+#endif
+                run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd, us);
+            }
         }
         if (P.trace && threadIdx.x == 0) {
             uint64_t *rec = P.trace + 4 * (size_t)t;
@@ -205,10 +210,11 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
             rec[2] = wall_clock64();
             rec[3] = blockIdx.x;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // every device-scope store of the task has completed before the counter moves
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&P.ver[T], kind == kTaskSolve ? slabs : 1u, __ATOMIC_RELEASE,
+            __hip_atomic_fetch_add(&P.ver[T], kind == kTaskSolve ? slabs : 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
@@ -256,7 +262,7 @@ __global__ void __launch_bounds__(kThreads) k_front_update(Plan Pk, int d, int k
     }
     const int T = ti * P.qt + tl, S = ks * P.qt + ls;
     const int u = update_index(P.pt, ti, tl, ks, ls);
-    run_update(P, kind, T, S, u, slab, L);
+    run_update(P, kind, T, S, u, slab, L, nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -25,14 +25,22 @@
 
 namespace trsyl {
 
+// Optional phase timestamps of the tile solve (built with -DTRSYL_PHASE_STAMPS): 80 wall-clock
+// words per tile, stored after the per-task trace records.
+#ifdef TRSYL_PHASE_STAMPS
+#define TRSYL_STAMP(ptr, idx) \
+    do { if ((ptr) && threadIdx.x == 0 && (idx) < 80) (ptr)[idx] = wall_clock64(); } while (0)
+#else
+#define TRSYL_STAMP(ptr, idx) do { (void)(ptr); } while (0)
+#endif
+
 constexpr int kLd = 17;          // leading dimension of the 16x16 LDS buffers
 constexpr int kMaxParts = kMaxLeaves > kWaves ? kMaxLeaves : kWaves;
 
-struct LeafLds {
-    double R[16 * kLd];
-    double Al[16 * kLd];
-    double Bl[16 * kLd];
-    int rI[16], cJ[16], rst[17], cst[17];
+struct LeafLds {                 // 17 x 17 each; row 16 and column 16 stay zero
+    double R[17 * kLd];
+    double Al[17 * kLd];
+    double Bl[17 * kLd];
 };
 
 struct SolveLds {
@@ -50,19 +58,31 @@ struct SolveLds {
     double red[kWaves];
 };
 
-// Leaf boundaries of a diagonal tile with `len` rows: nominal multiples of kLeaf, moved down by
-// one where T(b, b-1) != 0.  Returns the leaf count; off[count] = len.
-__device__ inline int leaf_offsets(const double *T, int64_t ld, int len, int *off)
+// Leaf boundaries of the diagonal tiles A_kk (mr rows) and B_ll (nc rows), computed by one wave:
+// nominal multiples of kLeaf, each moved down by one where T(b, b-1) != 0 so that no 2x2 block is
+// split.  A moved boundary that reaches the tile end is dropped.  Lanes 0..31 handle A, lanes
+// 32..63 handle B; the valid boundaries of each side form a prefix of the candidates.
+__device__ inline void leaf_offsets_wave(const double *Ad, int64_t lda, int mr, const double *Bd,
+                                         int64_t ldb, int nc, int *la, int *lb, int *nla, int *nlb)
 {
-    int cnt = 0;
-    off[cnt++] = 0;
-    for (int b = kLeaf; b < len; b += kLeaf) {
-        int bb = (T[(int64_t)(b - 1) * ld + b] != 0.0) ? b + 1 : b;
-        if (bb >= len) break;
-        off[cnt++] = bb;
+    const int lane = threadIdx.x & 63;
+    const bool isB = lane >= 32;
+    const int k = lane & 31;
+    const double *T = isB ? Bd : Ad;
+    const int64_t ld = isB ? ldb : lda;
+    const int len = isB ? nc : mr;
+    const int b = (k + 1) * kLeaf;
+    bool valid = false;
+    int bb = 0;
+    if (k < kMaxLeaves && b < len) {
+        bb = (ldg(T + (int64_t)(b - 1) * ld + b) != 0.0) ? b + 1 : b;
+        valid = bb < len;
     }
-    off[cnt] = len;
-    return cnt;
+    const uint64_t mask = __ballot(valid);
+    const int na = 1 + __popcll(mask & 0xFFFFFFFFull), nb = 1 + __popcll(mask >> 32);
+    if (valid) (isB ? lb : la)[k + 1] = bb;
+    if (lane == 0) { la[0] = 0; la[na] = mr; *nla = na; }
+    if (lane == 32) { lb[0] = 0; lb[nb] = nc; *nlb = nb; }
 }
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -103,7 +123,7 @@ __device__ __forceinline__ bool solve2_cp(double k00, double k01, double k10, do
 }
 
 // 4 unknowns (2x2 A-block with 2x2 B-block): K = I (x) A11 + B11^T (x) I on vec(Z).
-__device__ __noinline__ bool solve4_cp(const double a[4], const double b[4], double z[4], double smin)
+__device__ __forceinline__ bool solve4_cp(const double (&a)[4], const double (&b)[4], double (&z)[4], double smin)
 {
     double K[4][4], v[4];
     int perm[4] = {0, 1, 2, 3};
@@ -182,13 +202,21 @@ __device__ __noinline__ bool solve4_cp(const double a[4], const double b[4], dou
 }
 
 // ---------------------------------------------------------------------------------------------
-// Leaf solve (one wave): A_l Y + Y B_l = R on a leaf of nr x nc <= 16 x 16 held in L.R (ld 17),
-// with A_l, B_l in L.Al, L.Bl.  Block anti-diagonals s = 0, 1, ...: the blocks on diagonal s are
-// solved (a 1x1 block in its own lane; a block with 2 or 4 unknowns by the lane that owns its
-// top-left entry, from values published to LDS), then every pending entry subtracts the
-// contributions of the block just solved in its block column (below it) and in its block row
-// (left of it).  Lane (c = lane & 15, q = lane >> 4) owns rows q, q+4, q+8, q+12 of column c.
-// Returns 1 if the certificate held.
+// Leaf solve (one wave): A_l Y + Y B_l = R on a leaf of nr x nc <= 16 x 16 held in L.R, with
+// A_l, B_l in L.Al, L.Bl (17 x 17, ld 17; row 16 and column 16 of all three arrays hold zeros).
+// Block anti-diagonals s = 0, 1, ...: the blocks on diagonal s are solved (a 1x1 block in its own
+// lane; a block with 2 or 4 unknowns by the lane that owns its top-left entry, from values
+// published to LDS), then every pending entry subtracts the contributions of the block just
+// solved in its block column (below it) and in its block row (left of it).
+//
+// Lane (c = lane & 15, q = lane >> 4) owns rows q, q+4, q+8, q+12 of column c.  Those rows lie
+// in distinct block rows, so a lane finalises at most one entry per step.  The block structure
+// is kept as bit masks (first rows of blocks, first rows of 2x2 blocks), and each lane walks its
+// column source upwards and each entry's row source rightwards one block per step; a missing
+// source points at the zero row / column 16, so every contribution is four unconditional FMAs.
+// An entry stops changing once final.  The certificate bound is tracked as a running maximum:
+// the first non-finite value any step can produce is an infinity (all operands are finite and
+// divisors are at least smin), which the maximum keeps.  Returns 1 if the certificate held.
 // ---------------------------------------------------------------------------------------------
 __device__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc)
 {
@@ -196,84 +224,110 @@ __device__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc)
     const int c = lane & 15, q = lane >> 4;
     const bool rstart = (lane < nr) && (lane == 0 || L.Al[(lane - 1) * kLd + lane] == 0.0);
     const bool cstart = (lane < nc) && (lane == 0 || L.Bl[(lane - 1) * kLd + lane] == 0.0);
-    const uint64_t rmask = __ballot(rstart), cmask = __ballot(cstart);
-    const int na = __popcll(rmask), nb = __popcll(cmask);
-    if (lane < nr) L.rI[lane] = __popcll(rmask & ((2ull << lane) - 1)) - 1;
-    if (lane < nc) L.cJ[lane] = __popcll(cmask & ((2ull << lane) - 1)) - 1;
-    if (rstart) L.rst[__popcll(rmask & ((1ull << lane) - 1))] = lane;
-    if (cstart) L.cst[__popcll(cmask & ((1ull << lane) - 1))] = lane;
-    if (lane == 0) { L.rst[na] = nr; L.cst[nb] = nc; }
-    wave_sync_lds();
+    const uint32_t rmask = (uint32_t)__ballot(rstart), cmask = (uint32_t)__ballot(cstart);
+    const uint32_t m2 = rmask & ~(rmask >> 1) & ((1u << (nr - 1)) - 1u);   // 2x2 block rows
+    const uint32_t n2 = cmask & ~(cmask >> 1) & ((1u << (nc - 1)) - 1u);   // 2x2 block columns
+    const int na = __popc(rmask), nb = __popc(cmask);
+    const bool cvalid = c < nc;
+    const uint32_t cle = cmask & ((2u << c) - 1u);
+    const int Jc = __popc(cle) - 1;                  // my block column
+    const int cb0 = 31 - __clz(cle);                 // its first column
+    const int csz = 1 + ((n2 >> cb0) & 1);
+    const double bcc = L.Bl[c * kLd + c];
 
     int ok = 1;
-    const bool cvalid = c < nc;
-    const int Jc = cvalid ? L.cJ[c] : 0;
-    const int cb0 = cvalid ? L.cst[Jc] : 0;
-    const int csz = cvalid ? L.cst[Jc + 1] - cb0 : 0;
-    const double bcc = cvalid ? L.Bl[c * kLd + c] : 0.0;
-    double acc[4], dinv[4];
-    int Ir[4], fin[4];
-    bool single[4], owner[4], valid[4];
+    double vmax = 0.0;
+    double acc[4], dd[4];
+    int fin[4], rowst[4], cs[4], rsz[4];
+    bool own[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = q + 4 * i;
-        valid[i] = cvalid && r < nr;
-        Ir[i] = valid[i] ? L.rI[r] : 0;
-        const int rb0 = valid[i] ? L.rst[Ir[i]] : 0;
-        const int rsz = valid[i] ? L.rst[Ir[i] + 1] - rb0 : 0;
-        fin[i] = valid[i] ? (na - 1 - Ir[i]) + Jc : -1;
-        single[i] = rsz == 1 && csz == 1;
-        owner[i] = valid[i] && r == rb0 && c == cb0;
-        acc[i] = valid[i] ? L.R[c * kLd + r] : 0.0;
-        const double dd = valid[i] ? L.Al[r * kLd + r] + bcc : 1.0;
-        if (valid[i] && single[i] && fabs(dd) < smin) ok = 0;
-        dinv[i] = dd;
+        const bool valid = cvalid && r < nr;
+        const uint32_t rle = rmask & ((2u << r) - 1u);
+        const int Ir = __popc(rle) - 1;              // my block row
+        const int rb0 = 31 - __clz(rle);
+        rsz[i] = 1 + ((m2 >> rb0) & 1);
+        rowst[i] = na - 1 - Ir;                      // first step with a row source
+        fin[i] = valid ? rowst[i] + Jc : -1;         // step at which the entry is final
+        cs[i] = 0;
+        own[i] = valid && r == rb0 && c == cb0;
+        acc[i] = L.R[c * kLd + r];
+        dd[i] = L.Al[r * kLd + r] + bcc;
+        if (valid && rsz[i] == 1 && csz == 1 && fabs(dd[i]) < smin) ok = 0;
     }
+    int rsc = 31 - __clz(rmask);                     // first row of the column source block
     const int steps = na + nb - 1;
     for (int s = 0; s < steps; ++s) {
-        // finalise the blocks on anti-diagonal s: 1x1 blocks in place, larger ones published
-        bool multi = false;
+        // this step's sources and their coefficients (independent of the step's values)
+        const bool colv = s >= Jc && rsc >= 0;
+        const int ia0 = colv ? rsc : 16;
+        const int ia1 = (colv && ((m2 >> rsc) & 1)) ? rsc + 1 : 16;
+        double a0[4], a1[4], b0[4], b1[4];
+        int ib0[4], ib1[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            if (fin[i] != s) continue;
             const int r = q + 4 * i;
-            if (single[i]) {
-                const double y = acc[i] / dinv[i];
-                if (!(fabs(y) <= Tc)) ok = 0;
-                L.R[c * kLd + r] = y;
+            a0[i] = L.Al[ia0 * kLd + r];
+            a1[i] = L.Al[ia1 * kLd + r];
+            const bool rowv = s >= rowst[i] && cs[i] < cb0;
+            ib0[i] = rowv ? cs[i] : 16;
+            ib1[i] = (rowv && ((n2 >> cs[i]) & 1)) ? cs[i] + 1 : 16;
+            b0[i] = L.Bl[c * kLd + ib0[i]];
+            b1[i] = L.Bl[c * kLd + ib1[i]];
+        }
+        // the entry this lane finalises at step s, if any
+        bool act = false, ownk = false;
+        double ak = 0.0, dk = 1.0;
+        int rk = 0, rszk = 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (fin[i] == s) {
+                act = true;
+                ak = acc[i];
+                dk = dd[i];
+                rk = q + 4 * i;
+                rszk = rsz[i];
+                ownk = own[i];
+            }
+        }
+        bool multi = false;
+        if (act) {
+            double y = ak;
+            if (rszk == 1 && csz == 1) {
+                y = ak / dk;
+                vmax = fmax(vmax, fabs(y));
             } else {
-                L.R[c * kLd + r] = acc[i];
                 multi = true;
             }
+            L.R[c * kLd + rk] = y;
         }
         if (__ballot(multi)) {
             wave_sync_lds();
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (fin[i] != s || single[i] || !owner[i]) continue;
-                const int ra = q + 4 * i, rsz = L.rst[Ir[i] + 1] - ra;
+            if (multi && ownk) {
+                const int ra = rk;
                 double a[4], b[4], z[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int p = t & 1, pp = t >> 1;   // column-major 2x2 position (p, pp)
-                    a[t] = (p < rsz && pp < rsz) ? L.Al[(ra + pp) * kLd + ra + p] : 0.0;
+                    a[t] = (p < rszk && pp < rszk) ? L.Al[(ra + pp) * kLd + ra + p] : 0.0;
                     b[t] = (p < csz && pp < csz) ? L.Bl[(c + pp) * kLd + c + p] : 0.0;
-                    z[t] = (p < rsz && pp < csz) ? L.R[(c + pp) * kLd + ra + p] : 0.0;
+                    z[t] = (p < rszk && pp < csz) ? L.R[(c + pp) * kLd + ra + p] : 0.0;
                 }
                 bool good;
-                if (rsz == 2 && csz == 2) {
+                if (rszk == 2 && csz == 2) {
                     good = solve4_cp(a, b, z, smin);
-                } else if (rsz == 2) {   // (A11 + b I) z = r over the two rows
+                } else if (rszk == 2) {   // (A11 + b I) z = r over the two rows
                     good = solve2_cp(a[0] + b[0], a[2], a[1], a[3] + b[0], z[0], z[1], smin);
-                } else {                 // z (a I + B11) = r over the two columns
+                } else {                  // z (a I + B11) = r over the two columns
                     good = solve2_cp(a[0] + b[0], b[1], b[2], a[0] + b[3], z[0], z[2], smin);
                 }
                 if (!good) ok = 0;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int p = t & 1, pp = t >> 1;
-                    if (p < rsz && pp < csz) {
-                        if (!(fabs(z[t]) <= Tc)) ok = 0;
+                    if (p < rszk && pp < csz) {
+                        vmax = fmax(vmax, fabs(z[t]));
                         L.R[(c + pp) * kLd + ra + p] = z[t];
                     }
                 }
@@ -281,37 +335,36 @@ __device__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc)
         }
         wave_sync_lds();
         // contributions of the blocks solved at step s
-        const int Is = na - 1 - (s - Jc);                // block solved in my block column
-        const bool colsrc = cvalid && Is >= 0 && Is < na;
-        const int rs0 = colsrc ? L.rst[Is] : 0, rs1 = colsrc ? L.rst[Is + 1] : 0;
-        const double y0 = colsrc ? L.R[c * kLd + rs0] : 0.0;
-        const double y1 = (colsrc && rs1 - rs0 == 2) ? L.R[c * kLd + rs0 + 1] : 0.0;
+        const double y0 = L.R[c * kLd + ia0], y1 = L.R[c * kLd + ia1];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            if (!valid[i] || fin[i] <= s) continue;
             const int r = q + 4 * i;
             double v = acc[i];
-            if (colsrc && Is > Ir[i]) {
-                v = fma(-L.Al[rs0 * kLd + r], y0, v);
-                if (rs1 - rs0 == 2) v = fma(-L.Al[(rs0 + 1) * kLd + r], y1, v);
+            v = fma(-a0[i], y0, v);
+            v = fma(-a1[i], y1, v);
+            v = fma(-L.R[ib0[i] * kLd + r], b0[i], v);
+            v = fma(-L.R[ib1[i] * kLd + r], b1[i], v);
+            if (s < fin[i]) {
+                acc[i] = v;
+                vmax = fmax(vmax, fabs(v));
             }
-            const int Js = s - (na - 1 - Ir[i]);         // block solved in my block row
-            if (Js >= 0 && Js < Jc) {
-                const int cs0 = L.cst[Js], cs1 = L.cst[Js + 1];
-                v = fma(-L.R[cs0 * kLd + r], L.Bl[c * kLd + cs0], v);
-                if (cs1 - cs0 == 2) v = fma(-L.R[(cs0 + 1) * kLd + r], L.Bl[c * kLd + cs0 + 1], v);
-            }
-            if (!(fabs(v) <= Tc)) ok = 0;
-            acc[i] = v;
         }
+        // advance the sources by one block
+        if (colv) rsc -= (rsc >= 2 && ((m2 >> (rsc - 2)) & 1)) ? 2 : 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (s >= rowst[i] && cs[i] < cb0) cs[i] += 1 + ((n2 >> cs[i]) & 1);
     }
     wave_sync_lds();
+    if (!(vmax <= Tc)) ok = 0;
     return ok;
 }
 
 // ---------------------------------------------------------------------------------------------
-// One wave accumulates acc += Aop(0:nr, k) Bop(k, 0:ncl) over k in [k0, k1) with the next
-// 16-k chunk's operands loaded while the current chunk's MFMAs run.
+// One wave accumulates acc += Aop(0:nr, k) Bop(k, 0:ncl) over k in [k0, k1), 32 k at a time, the
+// next 32-k chunk's operands in flight while the current chunk's MFMAs run.  Lane (r, q) holds
+// k = kc + 4q + j and kc + 16 + 4q + j for j < 4 (the MFMA's k-permutation, see mfma16).  Loads
+// use clamped in-range addresses; out-of-range operands are replaced by zeros after the load.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void leaf_gemm(d4 &acc, const double *Aop, int64_t lda, int nr,
                                           const double *Bop, int64_t ldb, int ncl, int k0, int k1)
@@ -319,41 +372,98 @@ __device__ __forceinline__ void leaf_gemm(d4 &acc, const double *Aop, int64_t ld
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
     if (k0 >= k1) return;
-    double af[4], bf[4];
-    auto load = [&](int kc, double (&a)[4], double (&b)[4]) {
+    const bool va = r < nr, vb = r < ncl;
+    const double *Ar = Aop + (va ? r : 0);
+    const double *Bc = Bop + (int64_t)(vb ? r : 0) * ldb;
+    double af[8], bf[8];
+    auto load = [&](int kc, double (&a)[8], double (&b)[8]) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = kc + 4 * q + j;
-            a[j] = (r < nr && k < k1) ? Aop[(int64_t)k * lda + r] : 0.0;
-            b[j] = (r < ncl && k < k1) ? Bop[(int64_t)r * ldb + k] : 0.0;
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc + 16 * (j >> 2) + 4 * q + (j & 3);
+            const int kk = k < k1 ? k : k0;
+            a[j] = ldg(Ar + (int64_t)kk * lda);
+            b[j] = ldg(Bc + kk);
         }
     };
     load(k0, af, bf);
-    for (int kc = k0; kc < k1; kc += 16) {
-        double an[4], bn[4];
-        if (kc + 16 < k1) load(kc + 16, an, bn);
+    for (int kc = k0; kc < k1; kc += 32) {
+        double an[8], bn[8];
+        if (kc + 32 < k1) load(kc + 32, an, bn);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc = mfma16(bf[j], af[j], acc);
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc + 16 * (j >> 2) + 4 * q + (j & 3);
+            const bool kin = k < k1;
+            acc = mfma16((vb && kin) ? bf[j] : 0.0, (va && kin) ? af[j] : 0.0, acc);
+        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) { af[j] = an[j]; bf[j] = bn[j]; }
+        for (int j = 0; j < 8; ++j) { af[j] = an[j]; bf[j] = bn[j]; }
+    }
+}
+
+// Loads the inputs of leaf (I, J) that do not depend on other leaves: its diagonal blocks into
+// LL.Al / LL.Bl and its right-hand side into registers (lane (m, n0): entries (m, n0 + 4i)).
+__device__ __forceinline__ void leaf_inputs(const Plan &P, const double *Ad, const double *Bd,
+                                            const DevView &Y, const SolveLds &L, LeafLds &LL,
+                                            int I, int J, double (&rhs)[4])
+{
+    const int lane = threadIdx.x & 63;
+    const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
+    const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+        const bool in = mm < nr && nn < ncl;
+        const double v = ld_dev(Y, (int64_t)(lc0 + (in ? nn : 0)) * P.ldc + lr0 + (in ? mm : 0));
+        rhs[i] = in ? v : 0.0;
+    }
+#pragma unroll
+    for (int t0 = 0; t0 < 256; t0 += 64) {
+        const int t = t0 + lane, rr = t & 15, cc = t >> 4;
+        const bool ia = rr < nr && cc < nr && rr <= cc + 1;
+        const bool ib = rr < ncl && cc < ncl && rr <= cc + 1;
+        const double va = ldg(Ad + (int64_t)(lr0 + (ia ? cc : 0)) * P.lda + lr0 + (ia ? rr : 0));
+        const double vb = ldg(Bd + (int64_t)(lc0 + (ib ? cc : 0)) * P.ldb + lc0 + (ib ? rr : 0));
+        LL.Al[cc * kLd + rr] = ia ? va : 0.0;
+        LL.Bl[cc * kLd + rr] = ib ? vb : 0.0;
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Speculative tile solve.  Returns 1 if certified (tile holds Y with beta = 1).
+// Speculative tile solve.  Y (ld ldc) holds the right-hand side and is only read; the solution
+// is written to S (ld mr).  Returns 1 if certified (S holds Y with beta = 1).
 // ---------------------------------------------------------------------------------------------
-__device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd, double *Y,
-                               int mr_, int nc_, double smin, double Tc, SolveLds &L)
+__device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd, const DevView &Y,
+                               double *S, int mr_, int nc_, double smin, double Tc, SolveLds &L,
+                               uint64_t *stamp)
 {
     const int mr = uniform(mr_), nc = uniform(nc_);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) {
-        L.nla = leaf_offsets(Ad, P.lda, mr, L.la);
-        L.nlb = leaf_offsets(Bd, P.ldb, nc, L.lb);
-        L.fail = 0;
+    // warm the caches with the upper parts of A_kk and B_ll (one load per 128-byte line); the
+    // values are consumed by an empty asm at the end so the loads are kept
+    double warm = 0.0;
+    {
+        const int la = (mr + 15) >> 4, lb = (nc + 15) >> 4;
+        for (int t = threadIdx.x; t < mr * la + nc * lb; t += kThreads) {
+            if (t < mr * la) {
+                const int cc = t / la, rr = 16 * (t % la);
+                if (rr <= cc + 1) warm += ldg(Ad + (int64_t)cc * P.lda + rr);
+            } else {
+                const int u = t - mr * la, cc = u / lb, rr = 16 * (u % lb);
+                if (rr <= cc + 1) warm += ldg(Bd + (int64_t)cc * P.ldb + rr);
+            }
+        }
+    }
+    if (w == 0) leaf_offsets_wave(Ad, P.lda, mr, Bd, P.ldb, nc, L.la, L.lb, &L.nla, &L.nlb);
+    if (threadIdx.x == 0) L.fail = 0;
+    if (lane < 33) {                                 // zero row / column 16 of the leaf buffers
+        const int o = lane < 17 ? lane * kLd + 16 : 16 * kLd + (lane - 17);
+        L.leaf[w].R[o] = 0.0;
+        L.leaf[w].Al[o] = 0.0;
+        L.leaf[w].Bl[o] = 0.0;
     }
     __syncthreads();
     const int nla = uniform(L.nla), nlb = uniform(L.nlb);
+    const int64_t lds = mr;
     LeafLds &LL = L.leaf[w];
     int ok = 1;
     for (int d = 0; d < nla + nlb - 1; ++d) {
@@ -361,6 +471,8 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
         const int jhi = d < nlb - 1 ? d : nlb - 1;
         const int nleaf = jhi - jlo + 1;
         const int parts = nleaf >= kWaves ? 1 : kWaves / nleaf;
+        double rhs[4];
+        if (w < nleaf) leaf_inputs(P, Ad, Bd, Y, L, LL, nla - 1 - (d - (jlo + w)), jlo + w, rhs);
         // phase A: partial right-hand-side GEMMs, work item = leaf * parts + part
         for (int item = w; item < nleaf * parts; item += kWaves) {
             const int J = jlo + item / parts, part = item % parts;
@@ -375,12 +487,12 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             d4 acc = zero4();
             // first term: A(I, below) Y(below, J), chunks [c0, min(c1, n1))
             if (c0 < n1)
-                leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, Y + (int64_t)lc0 * P.ldc + kb,
-                          P.ldc, ncl, 16 * c0, c1 < n1 ? 16 * c1 : K1);
+                leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
+                          lds, ncl, 16 * c0, c1 < n1 ? 16 * c1 : K1);
             // second term: Y(I, left) B(left, J), chunks [max(c0, n1), c1) shifted by n1
             if (c1 > n1) {
                 const int s0 = (c0 > n1 ? c0 : n1) - n1, s1 = c1 - n1;
-                leaf_gemm(acc, Y + lr0, P.ldc, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 16 * s0,
+                leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 16 * s0,
                           16 * s1 < K2 ? 16 * s1 : K2);
             }
             double *pp = L.part[item];
@@ -388,10 +500,12 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             for (int i = 0; i < 4; ++i) pp[((lane >> 4) + 4 * i) * kLd + (lane & 15)] = acc[i];
         }
         __syncthreads();
+        TRSYL_STAMP(stamp, 4 + 2 * d);
         // phase B: wave J - jlo (mod kWaves) reduces its leaf's parts in order and solves it
         for (int li = w; li < nleaf; li += kWaves) {
             const int J = jlo + li;
             const int I = nla - 1 - (d - J);
+            if (li != w) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
             const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
             const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
 #pragma unroll
@@ -401,34 +515,61 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
                 if (mm < nr && nn < ncl) {
                     double g = 0.0;
                     for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
-                    v = Y[(int64_t)(lc0 + nn) * P.ldc + lr0 + mm] - g;
-                    if (!(fabs(v) <= Tc)) ok = 0;
+                    v = rhs[i] - g;
+                    if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
                 }
                 LL.R[nn * kLd + mm] = v;
-            }
-            for (int t = lane; t < 256; t += 64) {
-                const int rr = t & 15, cc = t >> 4;
-                LL.Al[cc * kLd + rr] = (rr < nr && cc < nr && rr <= cc + 1)
-                                           ? Ad[(int64_t)(lr0 + cc) * P.lda + lr0 + rr] : 0.0;
-                LL.Bl[cc * kLd + rr] = (rr < ncl && cc < ncl && rr <= cc + 1)
-                                           ? Bd[(int64_t)(lc0 + cc) * P.ldb + lc0 + rr] : 0.0;
             }
             wave_sync_lds();
             if (!leaf_solve(LL, nr, ncl, smin, Tc)) ok = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
-                if (mm < nr && nn < ncl) Y[(int64_t)(lc0 + nn) * P.ldc + lr0 + mm] = LL.R[nn * kLd + mm];
+                if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
             }
             wave_sync_lds();
         }
         if (!ok) L.fail = 1;
         __threadfence_block();
         __syncthreads();
+        TRSYL_STAMP(stamp, 5 + 2 * d);
         if (uniform(L.fail)) break;
     }
+    asm volatile("" ::"v"(warm));
     __syncthreads();
     return uniform(L.fail) ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------------------------
+// ||Y||_inf of an mr x nc tile read from src (ld lsrc), optionally copying it to dst (ld ldst)
+// on the way.  Thread t sums row t % mr over the columns congruent to t / mr, so consecutive
+// threads read consecutive rows; the partial row sums meet in LDS.  dst, when given, is shared
+// with other workgroups and written with device-scope stores.
+// ---------------------------------------------------------------------------------------------
+__device__ double tile_norm_copy(const double *src, int64_t lsrc, const DevView *dst, int64_t ldst,
+                                 int mr, int nc, SolveLds &L)
+{
+    double *part = &L.part[0][0];                    // kThreads doubles of scratch
+    const int g = mr <= kThreads ? kThreads / mr : 1;
+    const int t = threadIdx.x, rr = t % mr, p = t / mr;
+    double s = 0.0;
+    if (p < g) {
+        for (int cc = p; cc < nc; cc += g) {
+            const double v = ldg(src + (int64_t)cc * lsrc + rr);
+            if (dst) st_dev(*dst, (int64_t)cc * ldst + rr, v);
+            s += fabs(v);
+        }
+    }
+    part[t] = s;
+    __syncthreads();
+    double v = 0.0;
+    if (t < mr) {
+        double rs = 0.0;
+        for (int u = 0; u < g; ++u) rs += part[u * mr + t];
+        v = rs;
+    }
+    __syncthreads();
+    return wg_max(v, L.red);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -445,7 +586,7 @@ __device__ void scale_tile(double *Y, int64_t ldc, int mr, int nc, int s)
     __syncthreads();
 }
 
-__device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *Bd, double *Y,
+__device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *Bd, double *Y, int64_t ldy,
                                  int mr_, int nc_, double smin, SolveLds &L, int *pert)
 {
     const int mr = uniform(mr_), nc = uniform(nc_);
@@ -504,7 +645,7 @@ __device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *
                     const int p = t & 1, pp = t >> 1;
                     a[t] = (p < rsz && pp < rsz) ? Ad[(int64_t)(ra0 + pp) * P.lda + ra0 + p] : 0.0;
                     b[t] = (p < csz && pp < csz) ? Bd[(int64_t)(cb0 + pp) * P.ldb + cb0 + p] : 0.0;
-                    z[t] = (p < rsz && pp < csz) ? Y[(int64_t)(cb0 + pp) * P.ldc + ra0 + p] : 0.0;
+                    z[t] = (p < rsz && pp < csz) ? Y[(int64_t)(cb0 + pp) * ldy + ra0 + p] : 0.0;
                 }
                 const int sb = small_solve(rsz, csz, a, b, z, smin, pert);
                 for (int t = 0; t < 4; ++t) L.z[t] = z[t];
@@ -512,11 +653,11 @@ __device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *
             }
             __syncthreads();
             const int sb = uniform(L.zinfo[0]);
-            if (sb) { scale_tile(Y, P.ldc, mr, nc, sb); e += sb; }     // Y <- beta Y
+            if (sb) { scale_tile(Y, ldy, mr, nc, sb); e += sb; }     // Y <- beta Y
             if (tid == 0) {
                 for (int t = 0; t < 4; ++t) {
                     const int p = t & 1, pp = t >> 1;
-                    if (p < rsz && pp < csz) Y[(int64_t)(cb0 + pp) * P.ldc + ra0 + p] = L.z[t];
+                    if (p < rsz && pp < csz) Y[(int64_t)(cb0 + pp) * ldy + ra0 + p] = L.z[t];
                 }
             }
             __threadfence_block();
@@ -525,7 +666,7 @@ __device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *
                 double best = 0.0;
                 for (int p = 0; p < rsz; ++p) {
                     double s = 0.0;
-                    for (int pp = 0; pp < csz; ++pp) s += fabs(Y[(int64_t)(cb0 + pp) * P.ldc + ra0 + p]);
+                    for (int pp = 0; pp < csz; ++pp) s += fabs(Y[(int64_t)(cb0 + pp) * ldy + ra0 + p]);
                     best = fmax(best, s);
                 }
                 return best;
@@ -534,18 +675,18 @@ __device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *
                 double v = 0.0;
                 for (int r = tid; r < ra0; r += kThreads) {
                     double s = 0.0;
-                    for (int cc = cb0; cc < cb1; ++cc) s += fabs(Y[(int64_t)cc * P.ldc + r]);
+                    for (int cc = cb0; cc < cb1; ++cc) s += fabs(Y[(int64_t)cc * ldy + r]);
                     v = fmax(v, s);
                 }
                 const double ynorm = wg_max(v, L.red);
                 const int s1 = uniform(protect_update(ynorm, L.anorm_above[ka], znorm()));
-                if (s1) { scale_tile(Y, P.ldc, mr, nc, s1); e += s1; }
+                if (s1) { scale_tile(Y, ldy, mr, nc, s1); e += s1; }
                 for (int r = tid; r < ra0; r += kThreads) {
                     for (int cc = cb0; cc < cb1; ++cc) {
-                        double acc = Y[(int64_t)cc * P.ldc + r];
+                        double acc = Y[(int64_t)cc * ldy + r];
                         for (int rr = ra0; rr < ra1; ++rr)
-                            acc = fma(-Ad[(int64_t)rr * P.lda + r], Y[(int64_t)cc * P.ldc + rr], acc);
-                        Y[(int64_t)cc * P.ldc + r] = acc;
+                            acc = fma(-Ad[(int64_t)rr * P.lda + r], Y[(int64_t)cc * ldy + rr], acc);
+                        Y[(int64_t)cc * ldy + r] = acc;
                     }
                 }
                 __threadfence_block();
@@ -556,19 +697,19 @@ __device__ int tile_solve_robust(const Plan &P, const double *Ad, const double *
                 for (int j = lb + 1 + tid; j < nb; j += kThreads) {
                     for (int p = ra0; p < ra1; ++p) {
                         double s = 0.0;
-                        for (int cc = L.bs[j]; cc < L.bs[j + 1]; ++cc) s += fabs(Y[(int64_t)cc * P.ldc + p]);
+                        for (int cc = L.bs[j]; cc < L.bs[j + 1]; ++cc) s += fabs(Y[(int64_t)cc * ldy + p]);
                         v = fmax(v, s);
                     }
                 }
                 const double ynorm = wg_max(v, L.red);
                 const int s2 = uniform(protect_update(ynorm, znorm(), L.bnorm_right[lb]));
-                if (s2) { scale_tile(Y, P.ldc, mr, nc, s2); e += s2; }
+                if (s2) { scale_tile(Y, ldy, mr, nc, s2); e += s2; }
                 for (int cc = cb1 + tid; cc < nc; cc += kThreads) {
                     for (int p = ra0; p < ra1; ++p) {
-                        double acc = Y[(int64_t)cc * P.ldc + p];
+                        double acc = Y[(int64_t)cc * ldy + p];
                         for (int c2 = cb0; c2 < cb1; ++c2)
-                            acc = fma(-Y[(int64_t)c2 * P.ldc + p], Bd[(int64_t)cc * P.ldb + c2], acc);
-                        Y[(int64_t)cc * P.ldc + p] = acc;
+                            acc = fma(-Y[(int64_t)c2 * ldy + p], Bd[(int64_t)cc * P.ldb + c2], acc);
+                        Y[(int64_t)cc * ldy + p] = acc;
                     }
                 }
                 __threadfence_block();
@@ -588,13 +729,19 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
     double *scratch = uniptr(scratch_);
     const int T = uniform(T_);     // see run_update: keep barrier-enclosing branches uniform
     const int ti = T / P.qt, tl = T % P.qt;
-    const int r0 = P.rowoff[ti], mr = P.rowoff[ti + 1] - r0;
-    const int c0 = P.coloff[tl], nc = P.coloff[tl + 1] - c0;
+    const int r0 = uniform(P.rowoff[ti]), mr = uniform(P.rowoff[ti + 1]) - r0;
+    const int c0 = uniform(P.coloff[tl]), nc = uniform(P.coloff[tl + 1]) - c0;
     const int U = tile_updates(P, T);
     const int e_in = tile_exp_at(P, T, U);
     int e_syl = 0;
     double nrm = 0.0;
     int pert = 0;
+#ifdef TRSYL_PHASE_STAMPS
+    uint64_t *stamp = P.trace ? P.trace + 4 * (size_t)P.ntasks + 80 * (size_t)T : nullptr;
+#else
+    uint64_t *stamp = nullptr;
+#endif
+    TRSYL_STAMP(stamp, 0);
     if (mr > 0 && nc > 0) {
         const double *Ad = P.A + (int64_t)r0 * P.lda + r0;
         const double *Bd = P.B + (int64_t)c0 * P.ldb + c0;
@@ -605,48 +752,31 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         const double dB = P.bnorm[(size_t)tl * P.qt + tl];
         const double dB1 = P.bdiag1[tl];
         const double Tc = kOmega / (64.0 + 8.0 * (dA + dB1 + dB));
+        const DevView vY = dev_view(Y, P.ldc, mr, nc);
         int done = 0;
-        if (!(P.flags & 1)) {
-            int big = 0;     // the certificate's partial-sum bound needs |input| <= Tc too
+        // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
+        if (!(P.flags & 1) && *P.gmax < 0x1p1016)
+            done = uniform(tile_solve_fast(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));
+        TRSYL_STAMP(stamp, 2);
+        if (!done) {
+            // Algorithm 2 on a private copy of the tile (the fast path left Y untouched)
+            if (threadIdx.x == 0) atomicAdd(&P.stats[0], 1u);
             for (int t = threadIdx.x; t < mr * nc; t += kThreads) {
                 const int rr = t % mr, cc = t / mr;
-                const double v = Y[(int64_t)cc * P.ldc + rr];
-                scratch[t] = v;
-                if (!(fabs(v) <= Tc)) big = 1;
+                scratch[t] = ld_dev(vY, (int64_t)cc * P.ldc + rr);
             }
             __threadfence_block();
-            big = uniform(__syncthreads_or(big));
-            // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
-            if (!big && *P.gmax < 0x1p1016) done = uniform(tile_solve_fast(P, Ad, Bd, Y, mr, nc, smin, Tc, L));
-            if (!done) {
-                for (int t = threadIdx.x; t < mr * nc; t += kThreads) {
-                    const int rr = t % mr, cc = t / mr;
-                    Y[(int64_t)cc * P.ldc + rr] = scratch[t];
-                }
-                __threadfence_block();
-                __syncthreads();
-                pert = 0;
-            }
+            __syncthreads();
+            e_syl = tile_solve_robust(P, Ad, Bd, scratch, mr, mr, nc, smin, L, &pert);
         }
-        if (!done) {
-            if (threadIdx.x == 0) atomicAdd(&P.stats[0], 1u);
-            e_syl = tile_solve_robust(P, Ad, Bd, Y, mr, nc, smin, L, &pert);
-        }
-        // exact ||Y_kl||_inf
-        double v = 0.0;
-        for (int rr = threadIdx.x; rr < mr; rr += kThreads) {
-            double s = 0.0;
-            for (int cc = 0; cc < nc; ++cc) s += fabs(Y[(int64_t)cc * P.ldc + rr]);
-            v = fmax(v, s);
-        }
-        nrm = wg_max(v, L.red);
+        nrm = tile_norm_copy(scratch, mr, &vY, P.ldc, mr, nc, L);   // publish the tile, exact norm
+        TRSYL_STAMP(stamp, 3);
     }
     if (pert) set_status(P.status, kPerturbed);
     if (threadIdx.x == 0) {
-        double *ns = tile_norm_slot(P, T, U + 1);
-        ns[0] = nrm;
-        for (int s = 1; s < P.slabs; ++s) ns[s] = 0.0;
-        *tile_exp_slot(P, T, U + 1) = e_in + e_syl;
+        tile_norm_store(P, T, U + 1, 0, nrm);
+        for (int s = 1; s < P.slabs; ++s) tile_norm_store(P, T, U + 1, s, 0.0);
+        tile_exp_store(P, T, U + 1, e_in + e_syl);
     }
 }
 

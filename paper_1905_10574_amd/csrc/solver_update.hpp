@@ -17,8 +17,15 @@
 
 namespace trsyl {
 
+// Leading dimension of the LDS operand stages: 9 column blocks of 16 plus padding that shifts
+// consecutive k rows across the LDS banks.
+constexpr int kUS = 146;
+constexpr int kUK = 16;               // k per stage
+
 struct UpdateLds {
-    double rows[kWaves][kMaxSlabRB * 16];
+    double As[2][kUK][kUS];           // Aop(m, k) of the pass rows, k-major
+    double Bs[2][kUK][kUS];           // Bop(k, n) of the pass columns, k-major
+    double rs[kWaves][kMaxTile + 3];  // per-wave partial absolute row sums of the slab
     double red[kWaves];
 };
 
@@ -51,24 +58,42 @@ __device__ __forceinline__ double wg_max(double v, double *red)
     return r;
 }
 
+// Per-tile state written by other workgroups: read and written at device scope.
+__device__ __forceinline__ DevView tnorm_view(const Plan &P)
+{
+    return dev_view(P.tnorm, (uint64_t)2 * P.pt * P.qt * P.slabs * 8);
+}
+__device__ __forceinline__ DevView texp_view(const Plan &P)
+{
+    return dev_view(P.texp, (uint64_t)2 * P.pt * P.qt * 4);
+}
+__device__ __forceinline__ int64_t tnorm_index(const Plan &P, int T, int version)
+{
+    return ((int64_t)(version & 1) * P.pt * P.qt + T) * P.slabs;
+}
+__device__ __forceinline__ int64_t texp_index(const Plan &P, int T, int version)
+{
+    return (int64_t)(version & 1) * P.pt * P.qt + T;
+}
 __device__ __forceinline__ double tile_norm_at(const Plan &P, int T, int version)
 {
-    const double *p = P.tnorm + ((size_t)(version & 1) * P.pt * P.qt + T) * P.slabs;
+    const DevView v = tnorm_view(P);
+    const int64_t b = tnorm_index(P, T, version);
     double r = 0.0;
-    for (int s = 0; s < P.slabs; ++s) r = fmax(r, p[s]);
+    for (int s = 0; s < P.slabs; ++s) r = fmax(r, ld_dev(v, b + s));
     return r;
 }
 __device__ __forceinline__ int32_t tile_exp_at(const Plan &P, int T, int version)
 {
-    return P.texp[(size_t)(version & 1) * P.pt * P.qt + T];
+    return ld_dev_i32(texp_view(P), texp_index(P, T, version));
 }
-__device__ __forceinline__ double *tile_norm_slot(const Plan &P, int T, int version)
+__device__ __forceinline__ void tile_norm_store(const Plan &P, int T, int version, int slab, double v)
 {
-    return P.tnorm + ((size_t)(version & 1) * P.pt * P.qt + T) * P.slabs;
+    st_dev(tnorm_view(P), tnorm_index(P, T, version) + slab, v);
 }
-__device__ __forceinline__ int32_t *tile_exp_slot(const Plan &P, int T, int version)
+__device__ __forceinline__ void tile_exp_store(const Plan &P, int T, int version, int32_t e)
 {
-    return P.texp + (size_t)(version & 1) * P.pt * P.qt + T;
+    st_dev_i32(texp_view(P), texp_index(P, T, version), e);
 }
 
 // Row-block range of slab `slab` for a tile with `rows` rows.
@@ -79,111 +104,230 @@ __device__ __forceinline__ void slab_rows(int rows, int slabs, int slab, int *rb
     *rb_hi = (int)(((int64_t)(slab + 1) * rbt) / slabs);
 }
 
+// n blocks are covered by groups of 8; a remainder of a single block joins the last group, so
+// groups hold at most 9 blocks (a nominal 128 tile that grew by one row is one group).
+__device__ __forceinline__ int block_groups(int n) { return n <= 9 ? 1 : (n % 8 == 1 ? n / 8 : (n + 7) / 8); }
+__device__ __forceinline__ int group_size(int n, int g, int ng) { return g == ng - 1 ? n - 8 * g : 8; }
+
 // ---------------------------------------------------------------------------------------------
-// One wave accumulates acc[rb][cb] += sum_k Aop(m, k) Bop(k, n) for the rows
-// m = m0 + 16 rb + (lane & 15) (valid below mlim) and columns n = n0 + 16 cbs[cb] + ... with the
-// D^T mapping of device_common.hpp.  Operand values are scaled by 2^shA / 2^shB on load (exact
-// powers of two; 0 means no scaling).
+// Stage k-chunk [kc, kc + 16) of both operands of a pass into LDS buffer `buf`:
+//   As[k][m] = 2^shA Aop(m0 + m, kc + k) for m < Mp,  Bs[k][n] = 2^shB Bop(kc + k, n0 + n), n < Np,
+// zero elsewhere (rows / columns past the pass and k past K), so every MFMA input is finite.
+// Aop is column-major with leading dimension lda (consecutive threads read consecutive m), Bop
+// column-major with ldb (16 consecutive k per column).  SA / SB select device-scope loads for
+// the operand that other workgroups write.  Loads use clamped in-range addresses and a select.
 // ---------------------------------------------------------------------------------------------
-template <int RB, int CB>
-__device__ __forceinline__ void wave_gemm(d4 (&acc)[RB][CB], int nrb, int ncb,
-                                          const double *Aop, int64_t lda, int m0, int mlim,
-                                          const double *Bop, int64_t ldb, const int (&ncol)[CB],
-                                          int nlim, int K, int shA, int shB)
+template <bool SA, bool SB>
+struct StageRegs {
+    double a[5], b[5];
+};
+
+template <bool SA, bool SB>
+__device__ __forceinline__ void stage_load(StageRegs<SA, SB> &R, const double *Aop, const DevView &vA,
+                                           int64_t lda, int m0, int Mp, const double *Bop,
+                                           const DevView &vB, int64_t ldb, int n0, int Np, int kc, int K)
 {
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 15, q = lane >> 4;
-    for (int kc = 0; kc < K; kc += 16) {
-        double bf[CB][4], af[RB][4];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int nn = ncol[cb] + r;
-            const bool nok = (cb < ncb) && (nn < nlim);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = kc + 4 * q + j;
-                bf[cb][j] = (nok && k < K) ? Bop[(int64_t)nn * ldb + k] : 0.0;
-            }
+    for (int i = 0; i < 5; ++i) {
+        const int e = threadIdx.x + kThreads * i;
+        if (i == 4 && threadIdx.x >= kUK * 144 - 4 * kThreads) break;     // wave-uniform tail
+        {
+            const int m = e % 144, k = kc + e / 144;
+            const int mc = m < Mp ? m : 0, kk = k < K ? k : K - 1;
+            const int64_t idx = (int64_t)kk * lda + m0 + mc;
+            double v;
+            if constexpr (SA) v = ld_dev(vA, idx);
+            else v = ldg(Aop + idx);
+            R.a[i] = (m < Mp && k < K) ? v : 0.0;
         }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const int mm = m0 + 16 * rb + r;
-            const bool mok = (rb < nrb) && (mm < mlim);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = kc + 4 * q + j;
-                af[rb][j] = (mok && k < K) ? Aop[(int64_t)k * lda + mm] : 0.0;
-            }
+        {
+            const int k = kc + (e & 15), n = e >> 4;
+            const int nc_ = n < Np ? n : 0, kk = k < K ? k : K - 1;
+            const int64_t idx = (int64_t)(n0 + nc_) * ldb + kk;
+            double v;
+            if constexpr (SB) v = ld_dev(vB, idx);
+            else v = ldg(Bop + idx);
+            R.b[i] = (n < Np && k < K) ? v : 0.0;
         }
-        if (shA) {
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) af[rb][j] = ldexp(af[rb][j], shA);
-        }
-        if (shB) {
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bf[cb][j] = ldexp(bf[cb][j], shB);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                    if (rb < nrb && cb < ncb) acc[rb][cb] = mfma16(bf[cb][j], af[rb][j], acc[rb][cb]);
     }
 }
 
-// Epilogue of one group of row blocks: D = 2^shC C - acc on the valid entries, and the entries'
-// absolute values summed into rowsum[rb] (per lane; the lane's row is m0 + 16 rb + (lane & 15)).
-template <int RBg, int CB>
-__device__ __forceinline__ void slab_epilogue(const d4 (&acc)[RBg][CB], int nrbg, int m0, int rows,
-                                              int cols, const int (&ncol)[CB], int ncb, double *Ct,
-                                              int64_t ldc, int shC, double *rowsum)
+template <bool SA, bool SB>
+__device__ __forceinline__ void stage_store(const StageRegs<SA, SB> &R, UpdateLds &L, int buf,
+                                            int shA, int shB)
 {
-    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int rb = 0; rb < RBg; ++rb) {
-        const int mm = m0 + 16 * rb + (lane & 15);
-        if (rb >= nrbg || mm >= rows) continue;
+    for (int i = 0; i < 5; ++i) {
+        const int e = threadIdx.x + kThreads * i;
+        if (i == 4 && threadIdx.x >= kUK * 144 - 4 * kThreads) break;
+        L.As[buf][e / 144][e % 144] = shA ? ldexp(R.a[i], shA) : R.a[i];
+        L.Bs[buf][e & 15][e >> 4] = shB ? ldexp(R.b[i], shB) : R.b[i];
+    }
+}
+
+// Target block (brow, bcol) of a pass, in the MFMA result layout: lane (r, q) holds rows
+// m0 + 16 brow + r and columns n0 + 16 bcol + q + 4i.  Loads use clamped in-range addresses.
+__device__ __forceinline__ void load_target(double (&cv)[4], const DevView &Ct, int64_t ldc, int m0,
+                                            int Mp, int n0, int Np, int brow, int bcol)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int mm = m0 + 16 * brow + r;
+    const int mmc = mm < m0 + Mp ? mm : m0;
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            if (cb >= ncb) continue;
+    for (int i = 0; i < 4; ++i) {
+        const int nn = n0 + 16 * bcol + q + 4 * i;
+        const int nnc = nn < n0 + Np ? nn : n0;
+        cv[i] = ld_dev(Ct, (int64_t)nnc * ldc + mmc);
+    }
+}
+
+// D = 2^shC C - acc on the valid entries of the block, stored at device scope; the block's
+// absolute row sums are added to rs[row - rbase] (row tile-relative).
+__device__ __forceinline__ void store_target(const double (&cv)[4], const d4 &ac, int shC, const DevView &Ct,
+                                             int64_t ldc, int m0, int Mp, int n0, int Np, int brow,
+                                             int bcol, double *rs, int rbase)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int mm = m0 + 16 * brow + r;
+    const bool mok = mm < m0 + Mp;
+    double rsum = 0.0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int nn = ncol[cb] + (lane >> 4) + 4 * i;
-                if (nn < cols) {
-                    double *p = Ct + (int64_t)nn * ldc + mm;
-                    double c = *p;
-                    if (shC) c = ldexp(c, shC);
-                    const double d = c - acc[rb][cb][i];
-                    *p = d;
-                    rowsum[rb] += fabs(d);
-                }
-            }
+    for (int i = 0; i < 4; ++i) {
+        const int nn = n0 + 16 * bcol + q + 4 * i;
+        if (mok && nn < n0 + Np) {
+            const double c = shC ? ldexp(cv[i], shC) : cv[i];
+            const double d = c - ac[i];
+            st_dev(Ct, (int64_t)nn * ldc + mm, d);
+            rsum += fabs(d);
         }
     }
+    rsum += __shfl_xor(rsum, 16);
+    rsum += __shfl_xor(rsum, 32);
+    if (q == 0 && mok) rs[mm - rbase] += rsum;
 }
 
 // ---------------------------------------------------------------------------------------------
 // Execute one update slab.  kind: kTaskColUpdate or kTaskRowUpdate.  T target, S source (solved),
 // u the update's position in T's order (reads version u of T, writes version u+1).
+//
+// The slab's row blocks x the tile's column blocks are covered in passes of at most 9 x 9
+// blocks of 16 x 16.  In a pass, wave w = 4 wr + wc owns the 4 x 2 blocks rows 4wr.., columns
+// 2wc.. of the first 8 x 8, and a share of the ninth block row / column (at most three
+// blocks), all accumulated with v_mfma_f64_16x16x4 from LDS stages of 16 k that are double
+// buffered: the next stage's global loads are in flight while the current stage's MFMAs run.
 // ---------------------------------------------------------------------------------------------
+template <bool COL>
+__device__ __forceinline__ void update_passes(const Plan &P, const double *Aop, int64_t lda,
+                                              const double *Bop, int64_t ldb, int K, int shA,
+                                              int shB, int shC, double *Ct, int rows, int cols,
+                                              int rb_lo, int nrb, UpdateLds &L, uint64_t *ustamp)
+{
+    constexpr bool SA = !COL, SB = COL;     // the solved tile Y_S is the shared operand
+    const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int wr = w >> 2, wc = w & 3;
+    const int ncbt = (cols + 15) >> 4;
+    const int ngr = block_groups(nrb), ngc = block_groups(ncbt);
+    const int nkc = (K + kUK - 1) / kUK;
+    const DevView vA = dev_view(Aop, lda, rows, K), vB = dev_view(Bop, ldb, K, cols);
+    const DevView vC = dev_view(Ct, P.ldc, rows, cols);
+    for (int gr = 0; gr < ngr; ++gr) {
+        for (int gc = 0; gc < ngc; ++gc) {
+            const int R = group_size(nrb, gr, ngr), Cc = group_size(ncbt, gc, ngc);
+            const int m0 = 16 * (rb_lo + 8 * gr), n0 = 16 * 8 * gc;
+            const int Mp = (m0 + 16 * R < rows ? m0 + 16 * R : rows) - m0;
+            const int Np = (n0 + 16 * Cc < cols ? n0 + 16 * Cc : cols) - n0;
+            const int R8 = R < 8 ? R : 8, C8 = Cc < 8 ? Cc : 8;
+            // this wave's main blocks and extra blocks (ninth block row, then ninth column)
+            const int nrm = R8 - 4 * wr < 0 ? 0 : (R8 - 4 * wr > 4 ? 4 : R8 - 4 * wr);
+            const int ncm = C8 - 2 * wc < 0 ? 0 : (C8 - 2 * wc > 2 ? 2 : C8 - 2 * wc);
+            const int xrow = R == 9 ? Cc : 0;
+            const int nx = xrow + (Cc == 9 ? R8 : 0);
+            int xr[3], xc[3];
+            int nxw = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int e = w + kWaves * j;
+                xr[j] = e < xrow ? 8 : e - xrow;
+                xc[j] = e < xrow ? e : 8;
+                if (e < nx) nxw = j + 1;
+            }
+            d4 acc[4][2], accx[3];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) { acc[a][0] = zero4(); acc[a][1] = zero4(); }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) accx[j] = zero4();
+
+            StageRegs<SA, SB> SR;
+            stage_load<SA, SB>(SR, Aop, vA, lda, m0, Mp, Bop, vB, ldb, n0, Np, 0, K);
+            stage_store<SA, SB>(SR, L, 0, shA, shB);
+            __syncthreads();
+            if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[2] = wall_clock64();
+            for (int c = 0; c < nkc; ++c) {
+                const int buf = c & 1;
+                const bool more = c + 1 < nkc;
+                if (more) stage_load<SA, SB>(SR, Aop, vA, lda, m0, Mp, Bop, vB, ldb, n0, Np, kUK * (c + 1), K);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 4 * q + j;
+                    double av[4], bv[2];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) av[a] = L.As[buf][k][16 * (4 * wr + a) + r];
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) bv[b] = L.Bs[buf][k][16 * (2 * wc + b) + r];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+                            if (a < nrm && b < ncm) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+                        if (x < nxw)
+                            accx[x] = mfma16(L.Bs[buf][k][16 * xc[x] + r], L.As[buf][k][16 * xr[x] + r], accx[x]);
+                }
+                if (more) stage_store<SA, SB>(SR, L, buf ^ 1, shA, shB);
+                __syncthreads();
+            }
+
+            if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[3] = wall_clock64();
+            // epilogue: D = 2^shC C - acc, row sums into this wave's partials
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                double cm[4][4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (a < nrm && b < ncm) load_target(cm[a], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (a < nrm && b < ncm)
+                        store_target(cm[a], acc[a][b], shC, vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a,
+                                     2 * wc + b, L.rs[w], 16 * rb_lo);
+            }
+            double cx[3][4];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+                if (x < nxw) load_target(cx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+                if (x < nxw)
+                    store_target(cx[x], accx[x], shC, vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x], L.rs[w], 16 * rb_lo);
+        }
+    }
+}
+
 __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int S_, int u_, int slab_,
-                                       UpdateLds &L)
+                                       UpdateLds &L, uint64_t *ustamp)
 {
     const Plan P = uniform_plan(Pin);
+    if (ustamp && threadIdx.x == 0) ustamp[0] = wall_clock64();
     // callee arguments arrive in vector registers: make them (and all that derives from them,
     // including the branches around the barriers below) visibly uniform
     const int kind = uniform(kind_), T = uniform(T_), S = uniform(S_), u = uniform(u_);
     const int slab = uniform(slab_);
     const int ti = T / P.qt, tl = T % P.qt;
     const int si = S / P.qt, sl = S % P.qt;
-    const int r0 = P.rowoff[ti], rows = P.rowoff[ti + 1] - r0;
-    const int c0 = P.coloff[tl], cols = P.coloff[tl + 1] - c0;
+    const int r0 = uniform(P.rowoff[ti]), rows = uniform(P.rowoff[ti + 1]) - r0;
+    const int c0 = uniform(P.coloff[tl]), cols = uniform(P.coloff[tl + 1]) - c0;
 
     // scale decision (identical in every slab of this update)
     const int VS = tile_updates(P, S) + 1;
@@ -193,100 +337,71 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
     const double yn = tile_norm_at(P, S, VS);
     const int emax = eC > eY ? eC : eY;
     const double cs = ldexp(cn, eC - emax), ys = ldexp(yn, eY - emax);
+    const bool colu = kind == kTaskColUpdate;
     double tn;
-    const double *Aop;
-    const double *Bop;
-    int64_t lda_, ldb_;
     int K;
-    int shA = 0, shB = 0;
-    if (kind == kTaskColUpdate) {      // target (ti, tl) -= A(ti, si) * Y(si, tl)
+    if (colu) {      // target (ti, tl) -= A(ti, si) * Y(si, tl)
         tn = P.anorm[(size_t)ti * P.pt + si];
-        const int k0 = P.rowoff[si];
-        K = P.rowoff[si + 1] - k0;
-        Aop = P.A + (int64_t)k0 * P.lda + r0;
-        lda_ = P.lda;
-        Bop = P.C + (int64_t)c0 * P.ldc + k0;
-        ldb_ = P.ldc;
-    } else {                           // target (ti, tl) -= Y(ti, sl) * B(sl, tl)
+        K = uniform(P.rowoff[si + 1] - P.rowoff[si]);
+    } else {         // target (ti, tl) -= Y(ti, sl) * B(sl, tl)
         tn = P.bnorm[(size_t)sl * P.qt + tl];
-        const int k0 = P.coloff[sl];
-        K = P.coloff[sl + 1] - k0;
-        Aop = P.C + (int64_t)k0 * P.ldc + r0;
-        lda_ = P.ldc;
-        Bop = P.B + (int64_t)c0 * P.ldb + k0;
-        ldb_ = P.ldb;
+        K = uniform(P.coloff[sl + 1] - P.coloff[sl]);
     }
-    const int s = (kind == kTaskColUpdate) ? protect_update(cs, tn, ys) : protect_update(cs, ys, tn);
+    const int s = colu ? protect_update(cs, tn, ys) : protect_update(cs, ys, tn);
     const int enew = emax + s;
-    const int shC = eC - enew;        // <= 0
-    const int shY = eY - enew;        // <= 0
-    if (kind == kTaskColUpdate) shB = shY; else shA = shY;
+    const int shC = uniform(eC - enew);       // <= 0
+    const int shY = uniform(eY - enew);       // <= 0
     if (threadIdx.x == 0 && slab == 0 && (shC != 0 || shY != 0)) atomicAdd(&P.stats[1], 1u);
 
     int rb_lo, rb_hi;
     slab_rows(rows, P.slabs, slab, &rb_lo, &rb_hi);
     const int nrb = rb_hi - rb_lo;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ncbt = (cols + 15) >> 4;
-
-    constexpr int CB = kMaxColBlocksPerWave;
-    int ncol[CB];
-    int ncb = 0;
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        const int g = w + kWaves * cb;
-        ncol[cb] = 16 * g;
-        if (g < ncbt) ncb = cb + 1;
-    }
-    const bool active = rows > 0 && cols > 0 && nrb > 0 && ncb > 0;
     double *Ct = P.C + (int64_t)c0 * P.ldc + r0;
-    double rowsum[kMaxSlabRB];
-#pragma unroll
-    for (int rb = 0; rb < kMaxSlabRB; ++rb) rowsum[rb] = 0.0;
+    for (int t = threadIdx.x; t < kWaves * (kMaxTile + 3); t += kThreads) (&L.rs[0][0])[t] = 0.0;
+    __syncthreads();
+    if (ustamp && threadIdx.x == 0) ustamp[1] = wall_clock64();
 
-    if (active) {
-        // main group: up to four row blocks
-        const int n4 = nrb < 4 ? nrb : 4;
-        d4 acc[4][CB];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < CB; ++b) acc[a][b] = zero4();
-        if (K > 0)
-            wave_gemm<4, CB>(acc, n4, ncb, Aop, lda_, 16 * rb_lo, rows, Bop, ldb_, ncol, cols, K, shA, shB);
-        slab_epilogue<4, CB>(acc, n4, 16 * rb_lo, rows, cols, ncol, ncb, Ct, P.ldc, shC, rowsum);
-        if (nrb > 4) {   // ragged fifth row block of a tile one row longer than nominal
-            d4 acc1[1][CB];
-#pragma unroll
-            for (int b = 0; b < CB; ++b) acc1[0][b] = zero4();
-            if (K > 0)
-                wave_gemm<1, CB>(acc1, 1, ncb, Aop, lda_, 16 * (rb_lo + 4), rows, Bop, ldb_, ncol, cols, K,
-                                 shA, shB);
-            slab_epilogue<1, CB>(acc1, 1, 16 * (rb_lo + 4), rows, cols, ncol, ncb, Ct, P.ldc, shC, rowsum + 4);
+    if (rows > 0 && cols > 0 && nrb > 0 && K > 0) {
+        if (colu) {
+            const int k0 = uniform(P.rowoff[si]);
+            update_passes<true>(P, P.A + (int64_t)k0 * P.lda + r0, P.lda, P.C + (int64_t)c0 * P.ldc + k0,
+                                P.ldc, K, 0, shY, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
+        } else {
+            const int k0 = uniform(P.coloff[sl]);
+            update_passes<false>(P, P.C + (int64_t)k0 * P.ldc + r0, P.ldc, P.B + (int64_t)c0 * P.ldb + k0,
+                                 P.ldb, K, shY, 0, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
+        }
+    } else if (rows > 0 && cols > 0 && nrb > 0 && shC != 0) {
+        // an empty source still rescales the target to the common exponent
+        const int srows = (16 * rb_hi < rows ? 16 * rb_hi : rows) - 16 * rb_lo;
+        for (int t = threadIdx.x; t < srows; t += kThreads) {
+            double rs = 0.0;
+            const DevView vC = dev_view(Ct, P.ldc, rows, cols);
+            for (int nn = 0; nn < cols; ++nn) {
+                const int64_t idx = (int64_t)nn * P.ldc + 16 * rb_lo + t;
+                const double d = ldexp(ld_dev(vC, idx), shC);
+                st_dev(vC, idx, d);
+                rs += fabs(d);
+            }
+            L.rs[0][t] = rs;
         }
     }
-
-    // rows: lanes l, l^16, l^32, l^48 share a row; then across the waves through LDS
-#pragma unroll
-    for (int rb = 0; rb < kMaxSlabRB; ++rb) {
-        double v = rowsum[rb];
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
-        if (lane < 16) L.rows[w][rb * 16 + lane] = v;
-    }
     __syncthreads();
+    if (ustamp && threadIdx.x == 0) ustamp[4] = wall_clock64();
     double best = 0.0;
-    if (threadIdx.x < kMaxSlabRB * 16) {
-        double t = 0.0;
+    const int srows = (16 * rb_hi < rows ? 16 * rb_hi : rows) - 16 * rb_lo;
+    for (int t = threadIdx.x; t < srows; t += kThreads) {
+        double tot = 0.0;
 #pragma unroll
-        for (int ww = 0; ww < kWaves; ++ww) t += L.rows[ww][threadIdx.x];
-        best = t;
+        for (int ww = 0; ww < kWaves; ++ww) tot += L.rs[ww][t];
+        best = fmax(best, tot);
     }
     best = wg_max(best, L.red);
     if (threadIdx.x == 0) {
-        tile_norm_slot(P, T, u + 1)[slab] = best;
-        *tile_exp_slot(P, T, u + 1) = enew;
+        tile_norm_store(P, T, u + 1, slab, best);
+        tile_exp_store(P, T, u + 1, enew);
     }
+    if (ustamp && threadIdx.x == 0) ustamp[5] = wall_clock64();
 }
 
 }  // namespace trsyl
