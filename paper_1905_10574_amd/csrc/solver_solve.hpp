@@ -48,6 +48,8 @@ struct SolveLds {
     double part[kMaxParts][16 * kLd];   // split-K partial sums of the leaf GEMMs
     int la[kMaxLeaves + 1], lb[kMaxLeaves + 1];
     int nla, nlb;
+    int nsteps[kWaves];
+    uint32_t msteps[kWaves];
     int fail;
     // fallback
     int as[kMaxTile + 1], bs[kMaxTile + 1];
@@ -202,108 +204,160 @@ __device__ __forceinline__ bool solve4_cp(const double (&a)[4], const double (&b
 }
 
 // ---------------------------------------------------------------------------------------------
-// Leaf solve (one wave): A_l Y + Y B_l = R on a leaf of nr x nc <= 16 x 16 held in L.R, with
-// A_l, B_l in L.Al, L.Bl (17 x 17, ld 17; row 16 and column 16 of all three arrays hold zeros).
+// Leaf solve: A_l Y + Y B_l = R on a leaf of nr x nc <= 16 x 16 held in L.R, with A_l, B_l in
+// L.Al, L.Bl (17 x 17, ld 17; row 16 and column 16 of all three arrays hold zeros), by a group of
+// 16 / E lanes-rows: lane gl of the group (0 <= gl < 256 / E) owns column c = gl & 15 and rows
+// q, q + Q, ... (q = gl >> 4, Q = 16 / E), E entries.  Every wave of the workgroup runs the step
+// loop in lockstep (one barrier per step, a second one on steps that finalise a 2x2 block), so
+// groups may span waves; waves without a leaf (active == false) only take part in the barriers.
+//
 // Block anti-diagonals s = 0, 1, ...: the blocks on diagonal s are solved (a 1x1 block in its own
 // lane; a block with 2 or 4 unknowns by the lane that owns its top-left entry, from values
 // published to LDS), then every pending entry subtracts the contributions of the block just
-// solved in its block column (below it) and in its block row (left of it).
-//
-// Lane (c = lane & 15, q = lane >> 4) owns rows q, q+4, q+8, q+12 of column c.  Those rows lie
-// in distinct block rows, so a lane finalises at most one entry per step.  The block structure
-// is kept as bit masks (first rows of blocks, first rows of 2x2 blocks), and each lane walks its
-// column source upwards and each entry's row source rightwards one block per step; a missing
-// source points at the zero row / column 16, so every contribution is four unconditional FMAs.
-// An entry stops changing once final.  The certificate bound is tracked as a running maximum:
-// the first non-finite value any step can produce is an infinity (all operands are finite and
-// divisors are at least smin), which the maximum keeps.  Returns 1 if the certificate held.
+// solved in its block column (below it) and in its block row (left of it).  A lane's rows lie in
+// distinct block rows (Q >= 4), so it finalises at most one entry per step.  The block structure
+// is kept as bit masks; each lane walks its column source upwards and each entry's row source
+// rightwards one block per step, a missing source pointing at the zero row / column 16, so every
+// contribution is four unconditional FMAs.  An entry stops changing once final.  The certificate
+// bound is a running maximum: the first non-finite value a step can produce is an infinity (all
+// operands are finite, divisors at least smin), which the maximum keeps.  Returns 1 if the
+// certificate held for this lane.
 // ---------------------------------------------------------------------------------------------
-__device__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc)
+struct LeafMasks {
+    uint32_t rmask, cmask, m2, n2;   // first rows / columns of blocks, of 2x2 blocks
+    int na, nb;
+};
+// Steps s that finalise a block with 2 or 4 unknowns: block (Ib, Jb) is final at step
+// (na - 1 - Ib) + Jb, so a 2x2 block row Ib marks steps na - 1 - Ib + [0, nb) and a 2x2 block
+// column Jb marks steps Jb + [0, na).
+__device__ __forceinline__ uint32_t multi_steps(const LeafMasks &M)
+{
+    uint32_t ms = 0u;
+    for (uint32_t x = M.m2; x; x &= x - 1u) {
+        const int r = __ffs((int)x) - 1;
+        const int Ib = __popc(M.rmask & ((1u << r) - 1u));
+        ms |= ((1u << M.nb) - 1u) << (M.na - 1 - Ib);
+    }
+    for (uint32_t x = M.n2; x; x &= x - 1u) {
+        const int c = __ffs((int)x) - 1;
+        const int Jb = __popc(M.cmask & ((1u << c) - 1u));
+        ms |= ((1u << M.na) - 1u) << Jb;
+    }
+    return ms;
+}
+__device__ __forceinline__ LeafMasks leaf_masks(const LeafLds &L, int nr, int nc)
 {
     const int lane = threadIdx.x & 63;
-    const int c = lane & 15, q = lane >> 4;
     const bool rstart = (lane < nr) && (lane == 0 || L.Al[(lane - 1) * kLd + lane] == 0.0);
     const bool cstart = (lane < nc) && (lane == 0 || L.Bl[(lane - 1) * kLd + lane] == 0.0);
-    const uint32_t rmask = (uint32_t)__ballot(rstart), cmask = (uint32_t)__ballot(cstart);
-    const uint32_t m2 = rmask & ~(rmask >> 1) & ((1u << (nr - 1)) - 1u);   // 2x2 block rows
-    const uint32_t n2 = cmask & ~(cmask >> 1) & ((1u << (nc - 1)) - 1u);   // 2x2 block columns
-    const int na = __popc(rmask), nb = __popc(cmask);
-    const bool cvalid = c < nc;
+    LeafMasks M;
+    M.rmask = (uint32_t)__ballot(rstart);
+    M.cmask = (uint32_t)__ballot(cstart);
+    M.m2 = M.rmask & ~(M.rmask >> 1) & ((1u << (nr - 1)) - 1u);
+    M.n2 = M.cmask & ~(M.cmask >> 1) & ((1u << (nc - 1)) - 1u);
+    M.na = __popc(M.rmask);
+    M.nb = __popc(M.cmask);
+    return M;
+}
+
+// E entries per lane; E == 4 means one wave per leaf, which synchronises at wave level and runs
+// its own step count.  For E < 4 all waves step together: `steps` and `msteps` (the OR of the
+// groups' multi_steps masks) are the same in every wave.
+template <int E>
+__device__ int leaf_solve_group(LeafLds &L, int nr, int nc, double smin, double Tc, bool active,
+                                int gl, int steps, uint32_t msteps)
+{
+    constexpr bool kWG = E < 4;
+    constexpr int Q = 16 / E;
+    const int c = gl & 15, q = gl >> 4;
+    LeafMasks M{0u, 0u, 0u, 0u, 1, 1};
+    if (active) M = leaf_masks(L, nr, nc);
+    if (!kWG) {
+        steps = M.na + M.nb - 1;
+        msteps = multi_steps(M);
+    }
+    const uint32_t rmask = M.rmask, cmask = M.cmask, m2 = M.m2, n2 = M.n2;
+    const int na = M.na;
+    const bool cvalid = active && c < nc;
     const uint32_t cle = cmask & ((2u << c) - 1u);
     const int Jc = __popc(cle) - 1;                  // my block column
-    const int cb0 = 31 - __clz(cle);                 // its first column
+    const int cb0 = cle ? 31 - __clz(cle) : 0;       // its first column
     const int csz = 1 + ((n2 >> cb0) & 1);
-    const double bcc = L.Bl[c * kLd + c];
+    const double bcc = active ? L.Bl[c * kLd + c] : 1.0;
 
     int ok = 1;
     double vmax = 0.0;
-    double acc[4], dd[4];
-    int fin[4], rowst[4], cs[4], rsz[4];
-    bool own[4];
+    double acc[E], dd[E];
+    int fin[E], rowst[E], cs[E], rsz[E];
+    bool own[E];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = q + 4 * i;
+    for (int i = 0; i < E; ++i) {
+        const int r = q + Q * i;
         const bool valid = cvalid && r < nr;
         const uint32_t rle = rmask & ((2u << r) - 1u);
         const int Ir = __popc(rle) - 1;              // my block row
-        const int rb0 = 31 - __clz(rle);
+        const int rb0 = rle ? 31 - __clz(rle) : 0;
         rsz[i] = 1 + ((m2 >> rb0) & 1);
         rowst[i] = na - 1 - Ir;                      // first step with a row source
         fin[i] = valid ? rowst[i] + Jc : -1;         // step at which the entry is final
         cs[i] = 0;
         own[i] = valid && r == rb0 && c == cb0;
-        acc[i] = L.R[c * kLd + r];
-        dd[i] = L.Al[r * kLd + r] + bcc;
+        acc[i] = active ? L.R[c * kLd + r] : 0.0;
+        dd[i] = active ? L.Al[r * kLd + r] + bcc : 1.0;
         if (valid && rsz[i] == 1 && csz == 1 && fabs(dd[i]) < smin) ok = 0;
     }
-    int rsc = 31 - __clz(rmask);                     // first row of the column source block
-    const int steps = na + nb - 1;
+    int rsc = rmask ? 31 - __clz(rmask) : -1;       // first row of the column source block
     for (int s = 0; s < steps; ++s) {
-        // this step's sources and their coefficients (independent of the step's values)
-        const bool colv = s >= Jc && rsc >= 0;
-        const int ia0 = colv ? rsc : 16;
-        const int ia1 = (colv && ((m2 >> rsc) & 1)) ? rsc + 1 : 16;
-        double a0[4], a1[4], b0[4], b1[4];
-        int ib0[4], ib1[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = q + 4 * i;
-            a0[i] = L.Al[ia0 * kLd + r];
-            a1[i] = L.Al[ia1 * kLd + r];
-            const bool rowv = s >= rowst[i] && cs[i] < cb0;
-            ib0[i] = rowv ? cs[i] : 16;
-            ib1[i] = (rowv && ((n2 >> cs[i]) & 1)) ? cs[i] + 1 : 16;
-            b0[i] = L.Bl[c * kLd + ib0[i]];
-            b1[i] = L.Bl[c * kLd + ib1[i]];
-        }
-        // the entry this lane finalises at step s, if any
-        bool act = false, ownk = false;
-        double ak = 0.0, dk = 1.0;
+        bool multi = false, ownk = false;
         int rk = 0, rszk = 1;
+        int ia0 = 16, ia1 = 16;
+        bool colv = false;
+        double a0[E], a1[E], b0[E], b1[E];
+        int ib0[E], ib1[E];
+        if (active) {
+            // this step's sources and their coefficients (independent of the step's values)
+            colv = s >= Jc && rsc >= 0;
+            ia0 = colv ? rsc : 16;
+            ia1 = (colv && ((m2 >> rsc) & 1)) ? rsc + 1 : 16;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (fin[i] == s) {
-                act = true;
-                ak = acc[i];
-                dk = dd[i];
-                rk = q + 4 * i;
-                rszk = rsz[i];
-                ownk = own[i];
+            for (int i = 0; i < E; ++i) {
+                const int r = q + Q * i;
+                a0[i] = L.Al[ia0 * kLd + r];
+                a1[i] = L.Al[ia1 * kLd + r];
+                const bool rowv = s >= rowst[i] && cs[i] < cb0;
+                ib0[i] = rowv ? cs[i] : 16;
+                ib1[i] = (rowv && ((n2 >> cs[i]) & 1)) ? cs[i] + 1 : 16;
+                b0[i] = L.Bl[c * kLd + ib0[i]];
+                b1[i] = L.Bl[c * kLd + ib1[i]];
+            }
+            // the entry this lane finalises at step s, if any
+            bool act = false;
+            double ak = 0.0, dk = 1.0;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                if (fin[i] == s) {
+                    act = true;
+                    ak = acc[i];
+                    dk = dd[i];
+                    rk = q + Q * i;
+                    rszk = rsz[i];
+                    ownk = own[i];
+                }
+            }
+            if (act) {
+                double y = ak;
+                if (rszk == 1 && csz == 1) {
+                    y = ak / dk;
+                    vmax = fmax(vmax, fabs(y));
+                } else {
+                    multi = true;
+                }
+                L.R[c * kLd + rk] = y;
             }
         }
-        bool multi = false;
-        if (act) {
-            double y = ak;
-            if (rszk == 1 && csz == 1) {
-                y = ak / dk;
-                vmax = fmax(vmax, fabs(y));
-            } else {
-                multi = true;
-            }
-            L.R[c * kLd + rk] = y;
-        }
-        if (__ballot(multi)) {
-            wave_sync_lds();
+        if (kWG) __syncthreads();
+        else wave_sync_lds();
+        if ((msteps >> s) & 1u) {
             if (multi && ownk) {
                 const int ra = rk;
                 double a[4], b[4], z[4];
@@ -332,30 +386,32 @@ __device__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc)
                     }
                 }
             }
+            if (kWG) __syncthreads();
+            else wave_sync_lds();
         }
-        wave_sync_lds();
-        // contributions of the blocks solved at step s
-        const double y0 = L.R[c * kLd + ia0], y1 = L.R[c * kLd + ia1];
+        if (active) {
+            // contributions of the blocks solved at step s
+            const double y0 = L.R[c * kLd + ia0], y1 = L.R[c * kLd + ia1];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = q + 4 * i;
-            double v = acc[i];
-            v = fma(-a0[i], y0, v);
-            v = fma(-a1[i], y1, v);
-            v = fma(-L.R[ib0[i] * kLd + r], b0[i], v);
-            v = fma(-L.R[ib1[i] * kLd + r], b1[i], v);
-            if (s < fin[i]) {
-                acc[i] = v;
-                vmax = fmax(vmax, fabs(v));
+            for (int i = 0; i < E; ++i) {
+                const int r = q + Q * i;
+                double v = acc[i];
+                v = fma(-a0[i], y0, v);
+                v = fma(-a1[i], y1, v);
+                v = fma(-L.R[ib0[i] * kLd + r], b0[i], v);
+                v = fma(-L.R[ib1[i] * kLd + r], b1[i], v);
+                if (s < fin[i]) {
+                    acc[i] = v;
+                    vmax = fmax(vmax, fabs(v));
+                }
             }
-        }
-        // advance the sources by one block
-        if (colv) rsc -= (rsc >= 2 && ((m2 >> (rsc - 2)) & 1)) ? 2 : 1;
+            // advance the sources by one block
+            if (colv) rsc -= (rsc >= 2 && ((m2 >> (rsc - 2)) & 1)) ? 2 : 1;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (s >= rowst[i] && cs[i] < cb0) cs[i] += 1 + ((n2 >> cs[i]) & 1);
+            for (int i = 0; i < E; ++i)
+                if (s >= rowst[i] && cs[i] < cb0) cs[i] += 1 + ((n2 >> cs[i]) & 1);
+        }
     }
-    wave_sync_lds();
     if (!(vmax <= Tc)) ok = 0;
     return ok;
 }
@@ -501,33 +557,71 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
         }
         __syncthreads();
         TRSYL_STAMP(stamp, 4 + 2 * d);
-        // phase B: wave J - jlo (mod kWaves) reduces its leaf's parts in order and solves it
-        for (int li = w; li < nleaf; li += kWaves) {
-            const int J = jlo + li;
-            const int I = nla - 1 - (d - J);
-            if (li != w) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
-            const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
-            const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+        // phase B: the front's leaves in rounds.  A round takes up to 8 / G leaves with G waves
+        // each (G = 4, 2, 1 for at most 2, 4, 8 remaining leaves); wave k fills slot k with leaf
+        // li0 + k (its right-hand side minus the partial sums in order), the groups solve in
+        // lockstep, and wave k stores slot k to S.
+        for (int li0 = 0; li0 < nleaf;) {
+            const int rem = nleaf - li0;
+            const int G = rem <= 2 ? 4 : 1;
+            const int nl = rem < kWaves / G ? rem : kWaves / G;
+            if (w < nl) {
+                const int li = li0 + w, J = jlo + li, I = nla - 1 - (d - J);
+                if (li0 > 0) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
+                const int nr = L.la[I + 1] - L.la[I], ncl = L.lb[J + 1] - L.lb[J];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
-                double v = 0.0;
-                if (mm < nr && nn < ncl) {
-                    double g = 0.0;
-                    for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
-                    v = rhs[i] - g;
-                    if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
+                for (int i = 0; i < 4; ++i) {
+                    const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                    double v = 0.0;
+                    if (mm < nr && nn < ncl) {
+                        double g = 0.0;
+                        for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
+                        v = rhs[i] - g;
+                        if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
+                    }
+                    LL.R[nn * kLd + mm] = v;
                 }
-                LL.R[nn * kLd + mm] = v;
+                wave_sync_lds();
+                const LeafMasks M = leaf_masks(LL, nr, ncl);
+                if (lane == 0) {
+                    L.nsteps[w] = M.na + M.nb - 1;
+                    L.msteps[w] = multi_steps(M);
+                }
             }
-            wave_sync_lds();
-            if (!leaf_solve(LL, nr, ncl, smin, Tc)) ok = 0;
+            __syncthreads();
+            int steps = 0;
+            uint32_t msteps = 0u;
+            for (int k = 0; k < nl; ++k) {
+                steps = L.nsteps[k] > steps ? L.nsteps[k] : steps;
+                msteps |= L.msteps[k];
+            }
+            steps = uniform(steps);
+            msteps = uniform(msteps);
+            if (li0 == 0) TRSYL_STAMP(stamp, 40 + 2 * d);
+            const int k = w / G;
+            const bool active = k < nl;
+            const int gl = (w % G) * 64 + lane;
+            const int ks = active ? k : 0;
+            const int Jk = jlo + li0 + ks, Ik = nla - 1 - (d - Jk);
+            const int nrk = L.la[Ik + 1] - L.la[Ik], nck = L.lb[Jk + 1] - L.lb[Jk];
+            int okk;
+            if (G == 4) okk = leaf_solve_group<1>(L.leaf[ks], nrk, nck, smin, Tc, active, gl, steps, msteps);
+            else if (G == 2) okk = leaf_solve_group<2>(L.leaf[ks], nrk, nck, smin, Tc, active, gl, steps, msteps);
+            else okk = leaf_solve_group<4>(L.leaf[ks], nrk, nck, smin, Tc, active, gl, steps, msteps);
+            if (!okk) ok = 0;
+            __syncthreads();
+            if (li0 == 0) TRSYL_STAMP(stamp, 41 + 2 * d);
+            if (w < nl) {
+                const int li = li0 + w, J = jlo + li, I = nla - 1 - (d - J);
+                const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
+                const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
-                if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
+                for (int i = 0; i < 4; ++i) {
+                    const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                    if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
+                }
             }
-            wave_sync_lds();
+            li0 += nl;
         }
         if (!ok) L.fail = 1;
         __threadfence_block();
