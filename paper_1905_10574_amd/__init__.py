@@ -12,7 +12,7 @@ import os
 
 import torch
 
-__all__ = ["Opts", "lib", "solve", "solve_async", "adjoint", "grad", "residual", "solve_batched",
+__all__ = ["Opts", "lib", "solve", "solve_async", "adjoint", "adjoint_async", "grad", "residual", "trsyl",
            "debug_protect_update", "debug_protect_division", "TrsylFunction", "workspace_size",
            "FP64", "FP32_REFINE", "SCHED_DAG", "SCHED_FRONTS"]
 
@@ -174,3 +174,111 @@ def debug_protect_division(args) -> list[int]:
     if rc:
         raise RuntimeError(rc)
     return out.cpu().tolist()
+
+
+def adjoint_async(A, B, W, opts: Opts | None = None):
+    """Enqueue the adjoint solve A^T G + G B^T = alpha_G W.  Returns (Gs, eG, info) device tensors
+    with Gs the column-major storage of G (G = Gs.t())."""
+    opts = opts or make_opts()
+    Ac = colmajor(A)
+    dev = Ac.device
+    Bc = colmajor(B, dev)
+    Gc = colmajor(W, dev)
+    m, n = Gc.shape[1], Gc.shape[0]
+    e = torch.zeros(1, dtype=torch.int64, device=dev)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = int(lib().trsyl_adjoint_workspace_size(m, n, ctypes.byref(opts)))
+    ws_keep, ws_ptr = _aligned_workspace(need, dev)
+    rc = lib().trsyl_robust_adjoint(m, n, Ac.data_ptr(), max(1, m), Bc.data_ptr(), max(1, n),
+                                    Gc.data_ptr(), max(1, m), e.data_ptr(), sc.data_ptr(),
+                                    info.data_ptr(), ctypes.byref(opts), ws_ptr, need, _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_robust_adjoint rejected its arguments: {rc}")
+    adjoint_async._keep = (Ac, Bc, ws_keep)
+    return Gc, e, info
+
+
+def adjoint(A, B, W, **kw):
+    """Adjoint solve; returns (G, eG, info) with A^T G + G B^T = 2^-eG W."""
+    Gc, e, info = adjoint_async(A, B, W, make_opts(**kw))
+    torch.cuda.synchronize(Gc.device)
+    return Gc.t(), int(e.item()), int(info.item())
+
+
+def grad(A, B, Y, eY, G, eG):
+    """Gradient products for L = <W, Y> (Y the scaled forward output, alpha_Y = 2^-eY fixed) from the
+    adjoint output G (A^T G + G B^T = 2^-eG W): returns (dA, dB, dC) on the device, dA and dB
+    masked to the quasi-triangular patterns of A and B.  eY, eG: ints or int64 device tensors."""
+    Ac = colmajor(A)
+    dev = Ac.device
+    Bc = colmajor(B, dev)
+    Yc = colmajor(Y, dev)
+    Gc = colmajor(G, dev)
+    m, n = Yc.shape[1], Yc.shape[0]
+    eYt = eY if isinstance(eY, torch.Tensor) else torch.tensor([int(eY)], dtype=torch.int64, device=dev)
+    eGt = eG if isinstance(eG, torch.Tensor) else torch.tensor([int(eG)], dtype=torch.int64, device=dev)
+    dA = torch.empty(m, m, dtype=torch.float64, device=dev)    # column-major storage
+    dB = torch.empty(n, n, dtype=torch.float64, device=dev)
+    dC = torch.empty(n, m, dtype=torch.float64, device=dev)
+    rc = lib().trsyl_grad(m, n, Ac.data_ptr(), max(1, m), Bc.data_ptr(), max(1, n), Yc.data_ptr(),
+                          max(1, m), eYt.data_ptr(), Gc.data_ptr(), max(1, m), eGt.data_ptr(),
+                          dA.data_ptr(), max(1, m), dB.data_ptr(), max(1, n), dC.data_ptr(),
+                          max(1, m), _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_grad rejected its arguments: {rc}")
+    grad._keep = (Ac, Bc, Yc, Gc, eYt, eGt)
+    return dA.t(), dB.t(), dC.t()
+
+
+def residual(A, B, Y, e, C) -> float:
+    """Eq. (9) relative residual of (alpha = 2^-e, Y), evaluated on the device in FP64."""
+    Ac = colmajor(A)
+    dev = Ac.device
+    Bc = colmajor(B, dev)
+    Yc = colmajor(Y, dev)
+    Cc = colmajor(C, dev)
+    m, n = Yc.shape[1], Yc.shape[0]
+    et = e if isinstance(e, torch.Tensor) else torch.tensor([int(e)], dtype=torch.int64, device=dev)
+    out = torch.zeros(1, dtype=torch.float64, device=dev)
+    need = int(lib().trsyl_residual_workspace_size(m, n))
+    ws_keep, ws_ptr = _aligned_workspace(need, dev)
+    rc = lib().trsyl_residual(m, n, Ac.data_ptr(), max(1, m), Bc.data_ptr(), max(1, n), Yc.data_ptr(),
+                              max(1, m), et.data_ptr(), Cc.data_ptr(), max(1, m), out.data_ptr(),
+                              ws_ptr, need, _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_residual rejected its arguments: {rc}")
+    torch.cuda.synchronize(dev)
+    del ws_keep
+    return float(out.item())
+
+
+class TrsylFunction(torch.autograd.Function):
+    """Y = trsyl(A, B, C): the robust solution of A Y + Y B = alpha C with alpha = 2^-e held fixed
+    (e is returned as a non-differentiable output).  The backward pass solves the adjoint
+    A^T G + G B^T = alpha_G dL/dY on the device and forms dA = -G~ Y^T (A's pattern),
+    dB = -Y^T G~ (B's pattern), dC = alpha G~ with G~ = G / alpha_G."""
+
+    @staticmethod
+    def forward(ctx, A, B, C, tile=None):
+        Yc, e, _, info = solve_async(A, B, C, make_opts(tile=tile))
+        torch.cuda.synchronize(Yc.device)
+        Y = Yc.t().contiguous()
+        ctx.save_for_backward(A, B, Y, e)
+        ctx.tile = tile
+        ctx.mark_non_differentiable(e)
+        ctx.c_dtype = C.dtype if isinstance(C, torch.Tensor) else torch.float64
+        return Y, e
+
+    @staticmethod
+    def backward(ctx, dY, de):
+        A, B, Y, e = ctx.saved_tensors
+        G, eG, info = adjoint(A, B, dY.to(torch.float64), tile=ctx.tile)
+        dA, dB, dC = grad(A, B, Y, e, G, eG)
+        torch.cuda.synchronize(Y.device)
+        return dA.to(A.dtype), dB.to(B.dtype), dC.to(ctx.c_dtype), None
+
+
+def trsyl(A, B, C, tile=None):
+    """Differentiable robust solve: returns (Y, e) with A Y + Y B = 2^-e C."""
+    return TrsylFunction.apply(A, B, C, tile)

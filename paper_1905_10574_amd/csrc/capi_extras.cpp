@@ -1,37 +1,202 @@
-// Entry points of include/trsyl.h that are not the forward FP64 solve.  Filled in as the
-// corresponding drivers land; until then they report "not available" (-100).
+// Entry points of include/trsyl.h beside the forward solve: the adjoint solve, the gradient
+// products and the eq. (9) residual.  The batched driver is in capi_batched.cpp and the
+// precision form in capi_refine.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
+
 #include "../../include/trsyl.h"
+#include "extras.hpp"
+#include "launch.hpp"
+
+using namespace trsyl;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+bool bad_ptr(const void *p) { return p == nullptr; }
+
+}  // namespace
 
 extern "C" {
 
-size_t trsyl_adjoint_workspace_size(int64_t, int64_t, const trsyl_opts *) { return 0; }
-int trsyl_robust_adjoint(int64_t, int64_t, const double *, int64_t, const double *, int64_t, double *,
-                         int64_t, int64_t *, double *, int32_t *, const trsyl_opts *, void *, size_t,
-                         trsyl_stream_t)
+// ---------------------------------------------------------------------------------------------
+// Adjoint: A^T G + G B^T = alpha W.  With P, Q the order reversals, Ah = P A^T P and Bh = Q B^T Q
+// are upper quasi-triangular, and Gh = P G Q solves Ah Gh + Gh Bh = alpha P W Q; W is flipped in
+// place, solved by the forward driver, and flipped back.  Workspace: the forward workspace, then
+// Ah (m x m) and Bh (n x n).
+// ---------------------------------------------------------------------------------------------
+size_t trsyl_adjoint_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts)
 {
-    return -100;
+    const size_t fw = trsyl_workspace_size(m, n, opts);
+    if (fw == 0) return 0;
+    return align_up(fw) + align_up(8 * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(m, 1)) +
+           align_up(8 * (size_t)std::max<int64_t>(n, 1) * std::max<int64_t>(n, 1));
 }
-int trsyl_grad(int64_t, int64_t, const double *, int64_t, const double *, int64_t, const double *,
-               int64_t, const int64_t *, const double *, int64_t, const int64_t *, double *, int64_t,
-               double *, int64_t, double *, int64_t, trsyl_stream_t)
+
+int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, const double *B,
+                         int64_t ldb, double *W, int64_t ldw, int64_t *scale_log2, double *scale,
+                         int32_t *info, const trsyl_opts *opts, void *workspace, size_t ws_bytes,
+                         trsyl_stream_t stream_)
 {
-    return -100;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && bad_ptr(A)) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (n > 0 && bad_ptr(B)) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (m > 0 && n > 0 && bad_ptr(W)) return -7;
+    if (ldw < std::max<int64_t>(1, m)) return -8;
+    if (bad_ptr(scale_log2)) return -9;
+    if (bad_ptr(info)) return -11;
+    const size_t fw = trsyl_workspace_size(m, n, opts);
+    if (fw == 0) return -12;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -13;
+    if (ws_bytes < trsyl_adjoint_workspace_size(m, n, opts)) return -14;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
+    char *ws = (char *)workspace;
+    double *Ah = (double *)(ws + align_up(fw));
+    double *Bh = (double *)(ws + align_up(fw) + align_up(8 * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(m, 1)));
+    const int mi = (int)m, ni = (int)n;
+    if (m > 0 && n > 0) {
+        if (launch_flip_transpose(A, lda, mi, Ah, stream) != hipSuccess) return -100;
+        if (launch_flip_transpose(B, ldb, ni, Bh, stream) != hipSuccess) return -100;
+        if (launch_flip(W, ldw, mi, ni, stream) != hipSuccess) return -100;
+    }
+    const int rc = trsyl_robust(m, n, Ah, std::max<int64_t>(1, m), Bh, std::max<int64_t>(1, n), W, ldw,
+                                scale_log2, scale, info, opts, workspace, fw, stream_);
+    if (rc != 0) return rc == -100 ? -100 : -12;
+    if (m > 0 && n > 0 && launch_flip(W, ldw, mi, ni, stream) != hipSuccess) return -100;
+    return 0;
 }
-size_t trsyl_batched_workspace_size(int32_t, const int64_t *, const int64_t *, const trsyl_opts *) { return 0; }
-int trsyl_robust_batched(int32_t, const int64_t *, const int64_t *, const double *const *, const int64_t *,
-                         const double *const *, const int64_t *, double *const *, const int64_t *,
-                         int64_t *, double *, int32_t *, const trsyl_opts *, void *, size_t, trsyl_stream_t)
+
+// ---------------------------------------------------------------------------------------------
+// Gradient products: with Gt = 2^eG G,
+//   dC = 2^-eY Gt,  dA = -Gt Y^T on A's pattern,  dB = -Y^T Gt on B's pattern.
+// ---------------------------------------------------------------------------------------------
+int trsyl_grad(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+               const double *Y, int64_t ldy, const int64_t *eY, const double *G, int64_t ldg,
+               const int64_t *eG, double *dA, int64_t ldda, double *dB, int64_t lddb, double *dC,
+               int64_t lddc, trsyl_stream_t stream_)
 {
-    return -100;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && bad_ptr(A)) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (n > 0 && bad_ptr(B)) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (m > 0 && n > 0 && bad_ptr(Y)) return -7;
+    if (ldy < std::max<int64_t>(1, m)) return -8;
+    if (bad_ptr(eY)) return -9;
+    if (m > 0 && n > 0 && bad_ptr(G)) return -10;
+    if (ldg < std::max<int64_t>(1, m)) return -11;
+    if (bad_ptr(eG)) return -12;
+    if (m > 0 && bad_ptr(dA)) return -13;
+    if (ldda < std::max<int64_t>(1, m)) return -14;
+    if (n > 0 && bad_ptr(dB)) return -15;
+    if (lddb < std::max<int64_t>(1, n)) return -16;
+    if (m > 0 && n > 0 && bad_ptr(dC)) return -17;
+    if (lddc < std::max<int64_t>(1, m)) return -18;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
+    const int mi = (int)m, ni = (int)n;
+    GemmDesc g{};
+    // dA (m x m) = -2^eG sum_k G(i, k) Y(j, k)
+    g.M = mi; g.N = mi; g.K = ni;
+    g.A = G; g.sAm = 1; g.sAk = ldg; g.triA = 0;
+    g.B = Y; g.sBk = ldy; g.sBn = 1; g.triB = 0;
+    g.Cin = nullptr; g.ldcin = 1;
+    g.Out = dA; g.ldo = ldda;
+    g.asign = -1.0; g.ae0 = 0; g.ae1 = 1; g.ae2 = 0; g.ep1 = eG; g.ep2 = eG;
+    g.csign = 0.0; g.ce0 = g.ce1 = g.ce2 = 0;
+    g.mask = 1; g.pat = A; g.ldpat = lda;
+    if (m > 0 && launch_gemm(g, stream) != hipSuccess) return -100;
+    // dB (n x n) = -2^eG sum_k Y(k, i) G(k, j)
+    g.M = ni; g.N = ni; g.K = mi;
+    g.A = Y; g.sAm = ldy; g.sAk = 1;
+    g.B = G; g.sBk = 1; g.sBn = ldg;
+    g.Out = dB; g.ldo = lddb;
+    g.pat = B; g.ldpat = ldb;
+    if (n > 0 && launch_gemm(g, stream) != hipSuccess) return -100;
+    if (m > 0 && n > 0 && launch_scale_copy(G, ldg, mi, ni, eG, eY, dC, lddc, stream) != hipSuccess) return -100;
+    return 0;
 }
-size_t trsyl_residual_workspace_size(int64_t, int64_t) { return 0; }
-int trsyl_residual(int64_t, int64_t, const double *, int64_t, const double *, int64_t, const double *,
-                   int64_t, const int64_t *, const double *, int64_t, double *, void *, size_t,
-                   trsyl_stream_t)
+
+// ---------------------------------------------------------------------------------------------
+// Eq. (9): with 2^sy > max|Y| and Ys = 2^-sy Y (the quotient is invariant under scaling Y and
+// alpha together), R = 2^-(e+sy) C - A Ys - Ys B, and
+//   out = ||R||_F / ((||A||_F + ||B||_F) ||Ys||_F + ||2^-(e+sy) C||_F),
+// every norm carried as 2^s sqrt(t) so nothing overflows.  A and B norms cover their quasi-
+// triangular parts (the only entries the solver reads).  Workspace: R (m x n), the partial sums,
+// and a few scalars.
+// ---------------------------------------------------------------------------------------------
+size_t trsyl_residual_workspace_size(int64_t m, int64_t n)
 {
-    return -100;
+    if (m < 0 || n < 0) return 0;
+    return align_up(8 * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(n, 1)) +
+           align_up(8 * (size_t)kNormParts) + 256;
+}
+
+int trsyl_residual(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                   const double *Y, int64_t ldy, const int64_t *e, const double *C, int64_t ldc,
+                   double *out, void *workspace, size_t ws_bytes, trsyl_stream_t stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && bad_ptr(A)) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (n > 0 && bad_ptr(B)) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (m > 0 && n > 0 && bad_ptr(Y)) return -7;
+    if (ldy < std::max<int64_t>(1, m)) return -8;
+    if (bad_ptr(e)) return -9;
+    if (m > 0 && n > 0 && bad_ptr(C)) return -10;
+    if (ldc < std::max<int64_t>(1, m)) return -11;
+    if (bad_ptr(out)) return -12;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -13;
+    if (ws_bytes < trsyl_residual_workspace_size(m, n)) return -14;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
+    if (m == 0 || n == 0) return launch_fill_zero(out, sizeof(double), stream) == hipSuccess ? 0 : -100;
+    const int mi = (int)m, ni = (int)n;
+    char *ws = (char *)workspace;
+    double *R = (double *)ws;
+    double *part = (double *)(ws + align_up(8 * (size_t)mi * ni));
+    char *sc = ws + align_up(8 * (size_t)mi * ni) + align_up(8 * (size_t)kNormParts);
+    int32_t *s5 = (int32_t *)sc;               // 5 exponents (R, A, B, Y, C)
+    double *t5 = (double *)(sc + 32);          // 5 sums of squares
+    int64_t *negsy = (int64_t *)(sc + 80);     // -sy
+
+    if (launch_norm(Y, ldy, mi, ni, 0, part, s5 + 3, t5 + 3, stream) != hipSuccess) return -100;
+    if (launch_neg_exp(s5 + 3, negsy, stream) != hipSuccess) return -100;
+    GemmDesc g{};
+    // R = 2^(-e - sy) C - 2^-sy A Y
+    g.M = mi; g.N = ni; g.K = mi;
+    g.A = A; g.sAm = 1; g.sAk = lda; g.triA = 1;
+    g.B = Y; g.sBk = 1; g.sBn = ldy; g.triB = 0;
+    g.Cin = C; g.ldcin = ldc;
+    g.Out = R; g.ldo = mi;
+    g.asign = -1.0; g.ae0 = 0; g.ae1 = 1; g.ae2 = 0;
+    g.csign = 1.0; g.ce0 = 0; g.ce1 = 1; g.ce2 = -1;
+    g.ep1 = negsy; g.ep2 = e;
+    g.mask = 0; g.pat = nullptr; g.ldpat = 1;
+    if (launch_gemm(g, stream) != hipSuccess) return -100;
+    // R -= 2^-sy Y B
+    g.K = ni;
+    g.A = Y; g.sAm = 1; g.sAk = ldy; g.triA = 0;
+    g.B = B; g.sBk = 1; g.sBn = ldb; g.triB = 1;
+    g.Cin = R; g.ldcin = mi;
+    g.csign = 1.0; g.ce0 = 0; g.ce1 = 0; g.ce2 = 0;
+    if (launch_gemm(g, stream) != hipSuccess) return -100;
+    if (launch_norm(R, mi, mi, ni, 0, part, s5 + 0, t5 + 0, stream) != hipSuccess) return -100;
+    if (launch_norm(A, lda, mi, mi, 1, part, s5 + 1, t5 + 1, stream) != hipSuccess) return -100;
+    if (launch_norm(B, ldb, ni, ni, 1, part, s5 + 2, t5 + 2, stream) != hipSuccess) return -100;
+    if (launch_norm(C, ldc, mi, ni, 0, part, s5 + 4, t5 + 4, stream) != hipSuccess) return -100;
+    if (launch_residual_final(s5, t5, e, out, stream) != hipSuccess) return -100;
+    return 0;
 }
 
 }  // extern "C"

@@ -1,0 +1,373 @@
+// Kernels behind the entry points other than the forward solve:
+//
+//  * order-reversal transposes that map the adjoint equation A^T G + G B^T = alpha W onto the
+//    forward solver (P A^T P and Q B^T Q are upper quasi-triangular when A and B are, with the
+//    1x1 / 2x2 block structure reversed; P, Q reverse the index order);
+//  * a general FP64 MFMA GEMM  Out = cs * Cin + as * Aop Bop  with strided operands, optional
+//    quasi-triangular operand structure (entries outside it are never read), an optional
+//    quasi-triangular output pattern, and power-of-two scales taken from exponents in device
+//    memory -- used for the gradient products dA = -G Y^T, dB = -Y^T G and for the residual of
+//    eq. (9);
+//  * scale-safe Frobenius norms (max first, then a sum of squares of power-of-two-scaled entries,
+//    reduced in a fixed order).
+#include "device_common.hpp"
+#include "extras.hpp"
+
+namespace trsyl {
+
+constexpr int kGT = 128;      // output tile of the GEMM
+constexpr int kGK = 16;       // k per LDS stage
+constexpr int kGS = kGT + 2;  // padded LDS row
+
+// ---------------------------------------------------------------------------------------------
+// Ah(p, q) = A(n-1-q, n-1-p) on and above the first subdiagonal, zero below.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_flip_transpose(const double *A, int64_t lda, int n, double *Ah)
+{
+    const int64_t tot = (int64_t)n * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(t % n), q = (int)(t / n);
+        double v = 0.0;
+        if (p <= q + 1) v = ldg(A + (int64_t)(n - 1 - p) * lda + (n - 1 - q));
+        stg(Ah + (int64_t)q * n + p, v);
+    }
+}
+
+// W(i, j) <-> W(m-1-i, n-1-j), in place.
+__global__ void k_flip(double *W, int64_t ldw, int m, int n)
+{
+    const int64_t tot = (int64_t)m * n, half = tot / 2;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < half;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        double *p = W + (int64_t)j * ldw + i;
+        double *q = W + (int64_t)(n - 1 - j) * ldw + (m - 1 - i);
+        const double a = ldg(p), b = ldg(q);
+        stg(p, b);
+        stg(q, a);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// GEMM.  One workgroup of 512 threads computes a 128 x 128 output tile: wave w = 4 wr + wc owns
+// the 4 x 2 blocks of 16 x 16 at rows 16 (4 wr) .., columns 16 (2 wc) .., accumulated with
+// v_mfma_f64_16x16x4 from double-buffered LDS stages of 16 k.  Operand values outside the
+// matrices or outside a quasi-triangular operand's structure are staged as zeros (and never
+// loaded).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double exp_scale(double sign, int e0, int e1, int e2, const int64_t *p1,
+                                            const int64_t *p2)
+{
+    int64_t e = e0;
+    if (e1) e += (int64_t)e1 * *p1;
+    if (e2) e += (int64_t)e2 * *p2;
+    if (e > 2100) e = 2100;
+    if (e < -2100) e = -2100;
+    return ldexp(sign, (int)e);
+}
+
+struct GemmLds {
+    double As[2][kGK][kGS];
+    double Bs[2][kGK][kGS];
+};
+
+__global__ void __launch_bounds__(512) k_gemm(GemmDesc g)
+{
+    __shared__ GemmLds L;
+    const int m0 = kGT * blockIdx.x, n0 = kGT * blockIdx.y;
+    const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int wr = w >> 2, wc = w & 3;
+    const double as = exp_scale(g.asign, g.ae0, g.ae1, g.ae2, g.ep1, g.ep2);
+    const double cs = g.Cin ? exp_scale(g.csign, g.ce0, g.ce1, g.ce2, g.ep1, g.ep2) : 0.0;
+    const int Mp = g.M - m0 < kGT ? g.M - m0 : kGT, Np = g.N - n0 < kGT ? g.N - n0 : kGT;
+
+    // k range that can contribute to this tile
+    int klo = 0, khi = g.K;
+    if (g.triA && m0 - 1 > klo) klo = m0 - 1;
+    if (g.triB && n0 + kGT + 1 < khi) khi = n0 + kGT + 1;
+    const bool below = g.mask && m0 > n0 + kGT;        // tile entirely below the output pattern
+
+    d4 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { acc[a][0] = zero4(); acc[a][1] = zero4(); }
+
+    if (!below && klo < khi) {
+        double ra[4], rb[4];
+        auto load = [&](int kc) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = threadIdx.x + 512 * i;       // 2048 = 16 x 128 elements each
+                {
+                    const int m = e & 127, k = kc + (e >> 7);
+                    const int gm = m0 + m;
+                    bool ok = m < Mp && k < khi;
+                    if (g.triA) ok = ok && k >= gm - 1;
+                    const double v = ldg(g.A + (int64_t)(ok ? gm : m0) * g.sAm + (int64_t)(ok ? k : klo) * g.sAk);
+                    ra[i] = ok ? v : 0.0;
+                }
+                {
+                    const int k = kc + (e & 15), n = e >> 4;
+                    const int gn = n0 + n;
+                    bool ok = n < Np && k < khi;
+                    if (g.triB) ok = ok && k <= gn + 1;
+                    const double v = ldg(g.B + (int64_t)(ok ? k : klo) * g.sBk + (int64_t)(ok ? gn : n0) * g.sBn);
+                    rb[i] = ok ? v : 0.0;
+                }
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = threadIdx.x + 512 * i;
+                L.As[buf][e >> 7][e & 127] = ra[i];
+                L.Bs[buf][e & 15][e >> 4] = rb[i];
+            }
+        };
+        const int nkc = (khi - klo + kGK - 1) / kGK;
+        load(klo);
+        store(0);
+        __syncthreads();
+        for (int c = 0; c < nkc; ++c) {
+            const int buf = c & 1;
+            const bool more = c + 1 < nkc;
+            if (more) load(klo + kGK * (c + 1));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 4 * q + j;
+                double av[4], bv[2];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = L.As[buf][k][16 * (4 * wr + a) + r];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bv[b] = L.Bs[buf][k][16 * (2 * wc + b) + r];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+        }
+    }
+
+    // epilogue (result lane layout: row 16 a + r, columns 16 b + q + 4 i)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = m0 + 16 * (4 * wr + a) + r;
+        if (i >= g.M) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = n0 + 16 * (2 * wc + b) + q + 4 * t;
+                if (j >= g.N) continue;
+                double v = as * acc[a][b][t];
+                if (g.Cin) v += cs * ldg(g.Cin + (int64_t)j * g.ldcin + i);
+                if (g.mask) {
+                    bool keep = i <= j;
+                    if (i == j + 1) keep = ldg(g.pat + (int64_t)j * g.ldpat + i) != 0.0;
+                    if (!keep) v = 0.0;
+                }
+                stg(g.Out + (int64_t)j * g.ldo + i, v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Norms.  part[b] of block b: the block's partial over a grid-stride range.  Pattern 1 restricts
+// to the quasi-triangular pattern of a square matrix (on or above the first subdiagonal).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+// pass 0: partial max |x|;  pass 1: partial sum of (x 2^-s)^2 with 2^s the power of two at or
+// above the max (s read from *sexp).
+__global__ void k_norm_part(const double *X, int64_t ld, int rows, int cols, int pattern, int pass,
+                            const int32_t *sexp, double *part)
+{
+    __shared__ double red[16];
+    const int64_t tot = (int64_t)rows * cols;
+    const int s = pass ? *sexp : 0;
+    double v = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % rows), j = (int)(t / rows);
+        if (pattern && i > j + 1) continue;
+        const double x = ldg(X + (int64_t)j * ld + i);
+        if (pass == 0) v = fmax(v, fabs(x));
+        else { const double y = ldexp(x, -s); v = fma(y, y, v); }
+    }
+    const double r = pass == 0 ? block_max(v, red) : block_sum(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// Reduces nparts partials in order.  pass 0: *sexp = the exponent s with 2^s >= max (0 for a
+// zero matrix) and a non-finite max is flagged by s = INT32_MAX.  pass 1: out[0] = sum, so the
+// norm is 2^s sqrt(out[0]).
+__global__ void k_norm_final(const double *part, int nparts, int pass, int32_t *sexp, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (pass == 0) {
+        double m = 0.0;
+        bool bad = false;
+        for (int i = 0; i < nparts; ++i) {
+            if (!(part[i] <= 1.7976931348623157e308)) bad = true;
+            m = fmax(m, part[i]);
+        }
+        int s = 0;
+        if (bad) s = 0x7FFFFFFF;
+        else if (m > 0.0) {
+            s = ilogb(m) + 1;                      // 2^s > m
+        }
+        *sexp = s;
+    } else {
+        double t = 0.0;
+        for (int i = 0; i < nparts; ++i) t += part[i];
+        out[0] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Residual quotient of eq. (9) from the norm pairs (2^s sqrt(t)) of R, A, B, Y and C, with R and
+// the Y, C scales described in trsyl_residual: Y is used as Ys = 2^-sy Y and alpha C as
+// 2^-(e + sy) C.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < 5; ++i)
+        if (s5[i] == 0x7FFFFFFF || !(t5[i] <= 1.7976931348623157e308)) { *out = __builtin_nan(""); return; }
+    // norms as (mantissa, exponent): R, A, B, Ys, aC
+    const int sy = s5[3];
+    double v[5];
+    int64_t x[5];
+    for (int i = 0; i < 5; ++i) { v[i] = sqrt(t5[i]); x[i] = s5[i]; }
+    x[3] -= sy;                    // Ys = 2^-sy Y
+    x[4] -= (*e + sy);             // 2^-(e + sy) C
+    // denominator D = (A + B) Ys + aC, in a common exponent
+    const int64_t xab = x[1] > x[2] ? x[1] : x[2];
+    const double ab = ldexp(v[1], (int)(x[1] - xab > -3000 ? x[1] - xab : -3000)) +
+                      ldexp(v[2], (int)(x[2] - xab > -3000 ? x[2] - xab : -3000));
+    const int64_t xp = xab + x[3];
+    const double p = ab * v[3];
+    const int64_t xd = xp > x[4] ? xp : x[4];
+    const double d = ldexp(p, (int)(xp - xd > -3000 ? xp - xd : -3000)) +
+                     ldexp(v[4], (int)(x[4] - xd > -3000 ? x[4] - xd : -3000));
+    if (d == 0.0) { *out = v[0] == 0.0 ? 0.0 : __builtin_inf(); return; }
+    int64_t xq = x[0] - xd;
+    if (xq > 3000) xq = 3000;
+    if (xq < -3000) xq = -3000;
+    *out = ldexp(v[0] / d, (int)xq);
+}
+
+// dC = 2^(eG - eY) G
+__global__ void k_scale_copy(const double *G, int64_t ldg_, int m, int n, const int64_t *eG,
+                             const int64_t *eY, double *dC, int64_t lddc)
+{
+    const double sc = exp_scale(1.0, 0, 1, -1, eG, eY);
+    const int64_t tot = (int64_t)m * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % m), j = (int)(t / m);
+        stg(dC + (int64_t)j * lddc + i, sc * ldg(G + (int64_t)j * ldg_ + i));
+    }
+}
+
+// -sy with 2^sy >= max|Y| as an int64 (the norm pass-0 exponent of Y)
+__global__ void k_neg_exp(const int32_t *s, int64_t *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = -(int64_t)(*s == 0x7FFFFFFF ? 0 : *s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------------
+static int grid_for(int64_t work, int per = 256)
+{
+    int64_t g = (work + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+hipError_t launch_flip_transpose(const double *A, int64_t lda, int n, double *Ah, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flip_transpose, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, A, lda, n, Ah);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(double *W, int64_t ldw, int m, int n, hipStream_t s)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flip, dim3(grid_for((int64_t)m * n / 2 + 1)), dim3(256), 0, s, W, ldw, m, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmDesc &g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    dim3 grid((g.M + kGT - 1) / kGT, (g.N + kGT - 1) / kGT);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(512), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double *G, int64_t ldg_, int m, int n, const int64_t *eG,
+                             const int64_t *eY, double *dC, int64_t lddc, hipStream_t s)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for((int64_t)m * n)), dim3(256), 0, s, G, ldg_, m, n, eG,
+                       eY, dC, lddc);
+    return hipGetLastError();
+}
+
+// 2^s sqrt(*t) = ||X||_F (pattern 1: quasi-triangular part).  part: kNormParts doubles.
+hipError_t launch_norm(const double *X, int64_t ld, int rows, int cols, int pattern, double *part,
+                       int32_t *s, double *t, hipStream_t st)
+{
+    const int nb = kNormParts;
+    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(512), 0, st, X, ld, rows, cols, pattern, 0, s, part);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, nb, 0, s, t);
+    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(512), 0, st, X, ld, rows, cols, pattern, 1, s, part);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, nb, 1, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_neg_exp, dim3(1), dim3(64), 0, st, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(64), 0, st, s5, t5, e, out);
+    return hipGetLastError();
+}
+
+}  // namespace trsyl

@@ -1,0 +1,51 @@
+// Descriptors and host-side launchers of the kernels in extras.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trsyl {
+
+constexpr int kNormParts = 512;   // partial sums per norm (fixed reduction order)
+
+// Out = cs * Cin + as * Aop Bop (M x N, K inner), with
+//   Aop(m, k) = A[m * sAm + k * sAk],  Bop(k, n) = B[k * sBk + n * sBn],
+//   triA: Aop is upper quasi-triangular (entries with k < m - 1 are zero and never read),
+//   triB: Bop is upper quasi-triangular (entries with k > n + 1 are zero and never read),
+//   as = asign 2^(ae0 + ae1 *ep1 + ae2 *ep2),  cs likewise (Cin may be null),
+//   mask: zero every output entry outside the quasi-triangular pattern of the square matrix
+//         pat (keep i <= j, and i == j + 1 where pat(j+1, j) != 0).
+// Cin may equal Out (each entry is read and then written by the same thread).
+struct GemmDesc {
+    int M, N, K;
+    const double *A;
+    int64_t sAm, sAk;
+    int triA;
+    const double *B;
+    int64_t sBk, sBn;
+    int triB;
+    const double *Cin;
+    int64_t ldcin;
+    double *Out;
+    int64_t ldo;
+    double asign;
+    int ae0, ae1, ae2;
+    double csign;
+    int ce0, ce1, ce2;
+    const int64_t *ep1, *ep2;
+    int mask;
+    const double *pat;
+    int64_t ldpat;
+};
+
+hipError_t launch_flip_transpose(const double *A, int64_t lda, int n, double *Ah, hipStream_t s);
+hipError_t launch_flip(double *W, int64_t ldw, int m, int n, hipStream_t s);
+hipError_t launch_gemm(const GemmDesc &g, hipStream_t s);
+hipError_t launch_scale_copy(const double *G, int64_t ldg_, int m, int n, const int64_t *eG,
+                             const int64_t *eY, double *dC, int64_t lddc, hipStream_t s);
+hipError_t launch_norm(const double *X, int64_t ld, int rows, int cols, int pattern, double *part,
+                       int32_t *s, double *t, hipStream_t st);
+hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st);
+hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out,
+                                 hipStream_t st);
+
+}  // namespace trsyl

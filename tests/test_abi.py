@@ -1,0 +1,66 @@
+"""The C-ABI library loads on a machine without a GPU and exports every function that
+include/trsyl.h declares; the host-only calls (defaults, workspace sizes, argument checks) work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trsyl.h")
+LIB = os.path.join(ROOT, "paper_1905_10574_amd", "libtrsyl.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(trsyl_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libtrsyl.so not built")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ["trsyl_robust", "trsyl_workspace_size", "trsyl_robust_adjoint", "trsyl_grad",
+                 "trsyl_robust_batched", "trsyl_residual", "trsyl_default_opts", "trsyl_version"]:
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls(lib):
+    import paper_1905_10574_amd as T
+    o = T.Opts()
+    lib.trsyl_default_opts(ctypes.byref(o))
+    assert o.tile_m == 128 and o.tile_n == 128 and o.precision == 0 and o.scheduler == 0
+    lib.trsyl_workspace_size.restype = ctypes.c_size_t
+    lib.trsyl_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(T.Opts)]
+    assert lib.trsyl_workspace_size(1000, 700, ctypes.byref(o)) > 0
+    assert lib.trsyl_workspace_size(-1, 7, ctypes.byref(o)) == 0
+    bad = T.Opts()
+    lib.trsyl_default_opts(ctypes.byref(bad))
+    bad.tile_m = 8                                  # below the supported range
+    assert lib.trsyl_workspace_size(100, 100, ctypes.byref(bad)) == 0
+    lib.trsyl_version.restype = ctypes.c_char_p
+    assert lib.trsyl_version().startswith(b"trsyl")
+
+
+def test_argument_errors_are_reported_without_a_device(lib):
+    """Invalid arguments are rejected on the host before anything is enqueued."""
+    P, I64 = ctypes.c_void_p, ctypes.c_int64
+    lib.trsyl_robust.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, P, P, P, P, ctypes.c_size_t, P]
+    dummy = ctypes.c_void_p(256)
+    assert lib.trsyl_robust(-1, 4, dummy, 4, dummy, 4, dummy, 4, dummy, None, dummy, None, dummy, 1 << 20, None) == -1
+    assert lib.trsyl_robust(4, 4, None, 4, dummy, 4, dummy, 4, dummy, None, dummy, None, dummy, 1 << 20, None) == -3
+    assert lib.trsyl_robust(4, 4, dummy, 3, dummy, 4, dummy, 4, dummy, None, dummy, None, dummy, 1 << 20, None) == -4
+    assert lib.trsyl_robust(4, 4, dummy, 4, dummy, 4, dummy, 4, None, None, dummy, None, dummy, 1 << 20, None) == -9
+    assert lib.trsyl_robust(4, 4, dummy, 4, dummy, 4, dummy, 4, dummy, None, dummy, None, dummy, 8, None) == -14
