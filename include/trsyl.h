@@ -64,7 +64,7 @@ typedef struct trsyl_opts {
     int32_t precision;   /* enum trsyl_precision */
     int32_t scheduler;   /* enum trsyl_scheduler */
     int32_t slabs;       /* row slabs per tile update task; 0 = default (1: whole tiles) */
-    int32_t max_sweeps;  /* refinement sweeps for TRSYL_FP32_REFINE; 0 = default 3 */
+    int32_t max_sweeps;  /* refinement sweeps for TRSYL_FP32_REFINE; 0 = default 3, < 0 = none */
     double refine_tol;   /* eq. (9) target for TRSYL_FP32_REFINE; 0 = default 1e-13 */
     int32_t workers;     /* persistent workgroups; 0 = one per compute unit */
     int32_t flags;       /* bit 0: force the robust (non-speculative) tile solve */

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/trsyl.h"
+#include "extras.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
@@ -61,7 +62,7 @@ int resolve(const trsyl_opts *o, Resolved *r, int argpos)
     if (r->precision != TRSYL_FP64 && r->precision != TRSYL_FP32_REFINE) return -argpos;
     r->scheduler = o->scheduler;
     if (r->scheduler != TRSYL_SCHED_DAG && r->scheduler != TRSYL_SCHED_FRONTS) return -argpos;
-    r->max_sweeps = o->max_sweeps ? o->max_sweeps : 3;
+    r->max_sweeps = o->max_sweeps ? (o->max_sweeps < 0 ? 0 : o->max_sweeps) : 3;
     r->refine_tol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
     r->workers = o->workers > 0 ? o->workers : 0;
     r->flags = o->flags;
@@ -254,6 +255,124 @@ bool bad_ptr(const void *p) { return p == nullptr; }
 
 }  // namespace
 
+namespace {
+
+// The tiled robust solve (Algorithm 4) on C in place; extra_flags adds plan flags (FP32 updates
+// for the precision form's solves).  Arguments are already checked.
+int solve_core(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+               double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+               const Resolved &r0, int extra_flags, char *ws, hipEvent_t *ev, uint64_t *trace,
+               hipStream_t stream)
+{
+    Resolved r = r0;
+    r.flags |= extra_flags;
+    Layout L = make_layout(std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), r);
+    Plan P = make_plan(m, n, A, lda, B, ldb, C, ldc, r, L, ws);
+    P.e_out = scale_log2;
+    P.scale_out = scale;
+    P.info_out = info;
+    P.trace = trace;
+    if (m == 0 || n == 0) {
+        P.pt = P.qt = 0;
+        if (launch_fill_zero(ws, kAlign, stream) != hipSuccess) return -100;
+        // finalize with no tiles writes e = 0, alpha = 1 and the (zero) status
+        P.status = (int32_t *)(ws + 8);
+        return launch_finalize(P, stream) == hipSuccess ? 0 : -100;
+    }
+    if (launch_fill_zero(ws + L.zero_begin, L.zero_end - L.zero_begin, stream) != hipSuccess) return -100;
+    if (launch_setup(P, stream) != hipSuccess) return -100;
+    if (r.scheduler == TRSYL_SCHED_DAG) {
+        const TaskCache *tc = get_tasks(L.pt, L.qt, r.slabs, L.workers);
+        if (!tc) return -100;
+        if (hipMemcpyAsync(ws + L.tasks, tc->pinned, tc->tasks.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            return -100;
+        if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
+        if (launch_dag(P, L.workers, stream) != hipSuccess) return -100;
+    } else {
+        if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
+        if (launch_fronts(P, stream) != hipSuccess) return -100;
+    }
+    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
+    if (launch_finalize(P, stream) != hipSuccess) return -100;
+    return 0;
+}
+
+size_t refine_extra(int64_t m, int64_t n)
+{
+    const size_t mn = 8 * (size_t)m * n;
+    return 2 * align_up(mn) + align_up(8 * (size_t)kNormParts) + kAlign;
+}
+
+// Precision form: the tiled solve with FP32-MFMA tile updates (tile solves, bounds and scale
+// decisions in FP64), then max_sweeps refinement sweeps in FP64.  Sweep: with 2^sy > max|Y|,
+//   R' = 2^-(e+sy) C0 - 2^-sy (A Y + Y B)            (FP64 MFMA GEMMs, C0 the original C)
+//   A D + D B = 2^-eD R'                              (the FP32-update solve, robust)
+//   Y <- 2^-(eD+x) Y + 2^(sy-x) D,  e <- e + eD + x  (so A Y + Y B = 2^-e C0 again; the extra
+//                                                      power of two x keeps Y in range)
+// All on the stream; no host synchronisation.
+int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                  double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                  const Resolved &r, char *ws, hipEvent_t *ev, hipStream_t stream)
+{
+    Resolved rc = r;
+    rc.precision = TRSYL_FP64;
+    const size_t core = make_layout(m, n, rc).total;
+    const size_t mn = 8 * (size_t)m * n;
+    double *C0 = (double *)(ws + core);
+    double *D = (double *)(ws + core + align_up(mn));
+    double *part = (double *)(ws + core + 2 * align_up(mn));
+    char *sc = ws + core + 2 * align_up(mn) + align_up(8 * (size_t)kNormParts);
+    int64_t *eD = (int64_t *)(sc + 0);
+    int64_t *negsy = (int64_t *)(sc + 8);
+    int32_t *infoD = (int32_t *)(sc + 16);
+    int32_t *sy = (int32_t *)(sc + 20);
+    double *tY = (double *)(sc + 24);
+    int32_t *sD = (int32_t *)(sc + 32);
+    const int mi = (int)m, ni = (int)n;
+    if (hipMemcpy2DAsync(C0, 8 * (size_t)m, C, 8 * (size_t)ldc, 8 * (size_t)m, (size_t)n,
+                         hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return -100;
+    if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
+    int rcode = solve_core(m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, rc, kFlagF32Updates, ws,
+                           nullptr, nullptr, stream);
+    if (rcode) return rcode;
+    for (int sweep = 0; sweep < r.max_sweeps; ++sweep) {
+        if (launch_norm(C, ldc, mi, ni, 0, part, sy, tY, stream) != hipSuccess) return -100;
+        if (launch_neg_exp(sy, negsy, stream) != hipSuccess) return -100;
+        GemmDesc g{};
+        g.M = mi; g.N = ni; g.K = mi;                 // D = 2^(-e-sy) C0 - 2^-sy A Y
+        g.A = A; g.sAm = 1; g.sAk = lda; g.triA = 1;
+        g.B = C; g.sBk = 1; g.sBn = ldc; g.triB = 0;
+        g.Cin = C0; g.ldcin = mi;
+        g.Out = D; g.ldo = mi;
+        g.sa1 = 0; g.sb1 = 1;                         // Y staged as 2^-sy Y
+        g.asign = -1.0; g.ae0 = 0; g.ae1 = 0; g.ae2 = 0;
+        g.csign = 1.0; g.ce0 = 0; g.ce1 = 1; g.ce2 = -1;
+        g.ep1 = negsy; g.ep2 = scale_log2;
+        g.mask = 0; g.pat = nullptr; g.ldpat = 1;
+        if (launch_gemm(g, stream) != hipSuccess) return -100;
+        g.K = ni;                                     // D -= 2^-sy Y B
+        g.A = C; g.sAm = 1; g.sAk = ldc; g.triA = 0;
+        g.B = B; g.sBk = 1; g.sBn = ldb; g.triB = 1;
+        g.sa1 = 1; g.sb1 = 0;
+        g.Cin = D; g.ldcin = mi;
+        g.ce1 = 0; g.ce2 = 0;
+        if (launch_gemm(g, stream) != hipSuccess) return -100;
+        rcode = solve_core(m, n, A, lda, B, ldb, D, m, eD, nullptr, infoD, rc, kFlagF32Updates, ws, nullptr,
+                           nullptr, stream);
+        if (rcode) return rcode;
+        if (launch_absmax_exp(D, m, mi, ni, part, sD, stream) != hipSuccess) return -100;
+        if (launch_refine_update(C, ldc, D, m, mi, ni, eD, negsy, sD, scale_log2, info, infoD, scale,
+                                 stream) != hipSuccess)
+            return -100;
+    }
+    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
+    return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 void trsyl_default_opts(trsyl_opts *o)
@@ -275,7 +394,9 @@ size_t trsyl_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts)
     Resolved r;
     if (m < 0 || n < 0 || resolve(opts, &r, 3)) return 0;
     if (m == 0 || n == 0) return kAlign;
-    return make_layout(m, n, r).total;
+    const size_t core = make_layout(m, n, r).total;
+    if (r.precision == TRSYL_FP64) return core;
+    return core + refine_extra(m, n);
 }
 
 int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
@@ -299,40 +420,13 @@ int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const doubl
     if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -13;
     const size_t need = trsyl_workspace_size(m, n, opts);
     if (ws_bytes < need) return -14;
-    if (r.precision != TRSYL_FP64) return -12;   // the refinement driver lives in refine.cpp
-
-    Layout L = make_layout(std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), r);
-    char *ws = (char *)workspace;
-    Plan P = make_plan(m, n, A, lda, B, ldb, C, ldc, r, L, ws);
-    P.e_out = scale_log2;
-    P.scale_out = scale;
-    P.info_out = info;
-    P.trace = opts ? opts->trace : nullptr;
-    if (m == 0 || n == 0) {
-        P.pt = P.qt = 0;
-        if (launch_fill_zero(ws, kAlign, stream) != hipSuccess) return -100;
-        // finalize with no tiles writes e = 0, alpha = 1 and the (zero) status
-        P.status = (int32_t *)(ws + 8);
-        return launch_finalize(P, stream) == hipSuccess ? 0 : -100;
-    }
-    if (launch_fill_zero(ws + L.zero_begin, L.zero_end - L.zero_begin, stream) != hipSuccess) return -100;
-    if (launch_setup(P, stream) != hipSuccess) return -100;
     hipEvent_t *ev = opts ? (hipEvent_t *)opts->profile_events : nullptr;
-    if (r.scheduler == TRSYL_SCHED_DAG) {
-        const TaskCache *tc = get_tasks(L.pt, L.qt, r.slabs, L.workers);
-        if (!tc) return -100;
-        if (hipMemcpyAsync(ws + L.tasks, tc->pinned, tc->tasks.size() * sizeof(uint64_t),
-                           hipMemcpyHostToDevice, stream) != hipSuccess)
-            return -100;
-        if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
-        if (launch_dag(P, L.workers, stream) != hipSuccess) return -100;
-    } else {
-        if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
-        if (launch_fronts(P, stream) != hipSuccess) return -100;
-    }
-    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
-    if (launch_finalize(P, stream) != hipSuccess) return -100;
-    return 0;
+    uint64_t *trace = opts ? opts->trace : nullptr;
+    if (r.precision == TRSYL_FP64 || m == 0 || n == 0)
+        return solve_core(m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, r, 0, (char *)workspace,
+                          ev, trace, stream);
+    return solve_refined(m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, r, (char *)workspace, ev,
+                         stream);
 }
 
 int trsyl_debug_protect_update(int32_t count, const double *in, int32_t *out, trsyl_stream_t s)

@@ -173,21 +173,23 @@ int trsyl_residual(int64_t m, int64_t n, const double *A, int64_t lda, const dou
     if (launch_norm(Y, ldy, mi, ni, 0, part, s5 + 3, t5 + 3, stream) != hipSuccess) return -100;
     if (launch_neg_exp(s5 + 3, negsy, stream) != hipSuccess) return -100;
     GemmDesc g{};
-    // R = 2^(-e - sy) C - 2^-sy A Y
+    // R = 2^(-e - sy) C - A Ys
     g.M = mi; g.N = ni; g.K = mi;
     g.A = A; g.sAm = 1; g.sAk = lda; g.triA = 1;
     g.B = Y; g.sBk = 1; g.sBn = ldy; g.triB = 0;
     g.Cin = C; g.ldcin = ldc;
     g.Out = R; g.ldo = mi;
-    g.asign = -1.0; g.ae0 = 0; g.ae1 = 1; g.ae2 = 0;
+    g.sa1 = 0; g.sb1 = 1;                      // Ys = 2^-sy Y, staged
+    g.asign = -1.0; g.ae0 = 0; g.ae1 = 0; g.ae2 = 0;
     g.csign = 1.0; g.ce0 = 0; g.ce1 = 1; g.ce2 = -1;
     g.ep1 = negsy; g.ep2 = e;
     g.mask = 0; g.pat = nullptr; g.ldpat = 1;
     if (launch_gemm(g, stream) != hipSuccess) return -100;
-    // R -= 2^-sy Y B
+    // R -= Ys B
     g.K = ni;
     g.A = Y; g.sAm = 1; g.sAk = ldy; g.triA = 0;
     g.B = B; g.sBk = 1; g.sBn = ldb; g.triB = 1;
+    g.sa1 = 1; g.sb1 = 0;
     g.Cin = R; g.ldcin = mi;
     g.csign = 1.0; g.ce0 = 0; g.ce1 = 0; g.ce2 = 0;
     if (launch_gemm(g, stream) != hipSuccess) return -100;

@@ -81,6 +81,8 @@ __global__ void __launch_bounds__(512) k_gemm(GemmDesc g)
     const int wr = w >> 2, wc = w & 3;
     const double as = exp_scale(g.asign, g.ae0, g.ae1, g.ae2, g.ep1, g.ep2);
     const double cs = g.Cin ? exp_scale(g.csign, g.ce0, g.ce1, g.ce2, g.ep1, g.ep2) : 0.0;
+    const double sa = g.sa1 ? exp_scale(1.0, 0, g.sa1, 0, g.ep1, g.ep2) : 1.0;
+    const double sb = g.sb1 ? exp_scale(1.0, 0, g.sb1, 0, g.ep1, g.ep2) : 1.0;
     const int Mp = g.M - m0 < kGT ? g.M - m0 : kGT, Np = g.N - n0 < kGT ? g.N - n0 : kGT;
 
     // k range that can contribute to this tile
@@ -105,7 +107,7 @@ __global__ void __launch_bounds__(512) k_gemm(GemmDesc g)
                     bool ok = m < Mp && k < khi;
                     if (g.triA) ok = ok && k >= gm - 1;
                     const double v = ldg(g.A + (int64_t)(ok ? gm : m0) * g.sAm + (int64_t)(ok ? k : klo) * g.sAk);
-                    ra[i] = ok ? v : 0.0;
+                    ra[i] = ok ? v * sa : 0.0;
                 }
                 {
                     const int k = kc + (e & 15), n = e >> 4;
@@ -113,7 +115,7 @@ __global__ void __launch_bounds__(512) k_gemm(GemmDesc g)
                     bool ok = n < Np && k < khi;
                     if (g.triB) ok = ok && k <= gn + 1;
                     const double v = ldg(g.B + (int64_t)(ok ? k : klo) * g.sBk + (int64_t)(ok ? gn : n0) * g.sBn);
-                    rb[i] = ok ? v : 0.0;
+                    rb[i] = ok ? v * sb : 0.0;
                 }
             }
         };
@@ -304,6 +306,43 @@ __global__ void k_neg_exp(const int32_t *s, int64_t *out)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Refinement step of the precision form: with 2^sy > max|Y| (sy = -*negsy), 2^sD > max|D| and
+//   x = max(0, max(sy - eD, sy + sD) + 1 - (1022 - 9)),
+// Y <- 2^-(eD + x) Y + 2^(sy - x) D,  e <- e + eD + x,  status <- max(status, correction status),
+// scale <- 2^-e.  Since A Y + Y B = 2^-e C - 2^sy R' and A D + D B = 2^-eD R', the new pair
+// satisfies A Y + Y B = 2^-(e + eD + x) C; x keeps every entry below 2^(1022-9), so tiles of up to
+// 512 columns keep their infinity norms below OMEGA.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_refine_update(double *Y, int64_t ldy, const double *D, int64_t ldd, int m, int n,
+                                const int64_t *eD, const int64_t *negsy, const int32_t *sD, int64_t *e,
+                                int32_t *info, const int32_t *infoD, double *scale)
+{
+    const int64_t sy = -*negsy;
+    const int64_t sd = *sD == 0x7FFFFFFF ? 0 : *sD;
+    int64_t top = sy - *eD;
+    if (sy + sd > top) top = sy + sd;
+    int64_t x = top + 1 - (1022 - 9);
+    if (x < 0) x = 0;
+    int64_t ay = *eD + x, ad = x - sy;
+    if (ay > 2100) ay = 2100;
+    if (ad > 2100) ad = 2100;
+    if (ad < -2100) ad = -2100;
+    const int64_t tot = (int64_t)m * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % m), j = (int)(t / m);
+        double *p = Y + (int64_t)j * ldy + i;
+        stg(p, ldexp(ldg(p), -(int)ay) + ldexp(ldg(D + (int64_t)j * ldd + i), -(int)ad));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t en = *e + *eD + x;
+        *e = en;
+        if (*infoD > *info) *info = *infoD;
+        if (scale) *scale = en > 1074 ? 0.0 : ldexp(1.0, -(int)en);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------------
 static int grid_for(int64_t work, int per = 256)
@@ -367,6 +406,24 @@ hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int6
                                  hipStream_t st)
 {
     hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(64), 0, st, s5, t5, e, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_update(double *Y, int64_t ldy, const double *D, int64_t ldd, int m, int n,
+                                const int64_t *eD, const int64_t *negsy, const int32_t *sD, int64_t *e,
+                                int32_t *info, const int32_t *infoD, double *scale, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refine_update, dim3(grid_for((int64_t)m * n)), dim3(256), 0, st, Y, ldy, D, ldd,
+                       m, n, eD, negsy, sD, e, info, infoD, scale);
+    return hipGetLastError();
+}
+
+// 2^s > max |X| (s = 0 for a zero matrix, INT32_MAX if non-finite).  part: kNormParts doubles.
+hipError_t launch_absmax_exp(const double *X, int64_t ld, int rows, int cols, double *part, int32_t *s,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm_part, dim3(kNormParts), dim3(512), 0, st, X, ld, rows, cols, 0, 0, s, part);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, kNormParts, 0, s, (double *)nullptr);
     return hipGetLastError();
 }
 

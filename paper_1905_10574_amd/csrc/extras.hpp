@@ -12,6 +12,8 @@ constexpr int kNormParts = 512;   // partial sums per norm (fixed reduction orde
 //   triA: Aop is upper quasi-triangular (entries with k < m - 1 are zero and never read),
 //   triB: Bop is upper quasi-triangular (entries with k > n + 1 are zero and never read),
 //   as = asign 2^(ae0 + ae1 *ep1 + ae2 *ep2),  cs likewise (Cin may be null),
+//   the A operand's values are staged times 2^(sa1 *ep1), the B operand's times 2^(sb1 *ep1)
+//   (exact power-of-two normalisation that keeps the products in range),
 //   mask: zero every output entry outside the quasi-triangular pattern of the square matrix
 //         pat (keep i <= j, and i == j + 1 where pat(j+1, j) != 0).
 // Cin may equal Out (each entry is read and then written by the same thread).
@@ -27,6 +29,7 @@ struct GemmDesc {
     int64_t ldcin;
     double *Out;
     int64_t ldo;
+    int sa1, sb1;
     double asign;
     int ae0, ae1, ae2;
     double csign;
@@ -47,5 +50,11 @@ hipError_t launch_norm(const double *X, int64_t ld, int rows, int cols, int patt
 hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st);
 hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out,
                                  hipStream_t st);
+
+hipError_t launch_refine_update(double *Y, int64_t ldy, const double *D, int64_t ldd, int m, int n,
+                                const int64_t *eD, const int64_t *negsy, const int32_t *sD, int64_t *e,
+                                int32_t *info, const int32_t *infoD, double *scale, hipStream_t st);
+hipError_t launch_absmax_exp(const double *X, int64_t ld, int rows, int cols, double *part, int32_t *s,
+                             hipStream_t st);
 
 }  // namespace trsyl

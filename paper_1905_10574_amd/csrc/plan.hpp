@@ -14,6 +14,10 @@ constexpr int kMaxLeaves = 18;       // ceil(257 / 15)
 constexpr int kMaxSlabRB = 5;        // 16-row blocks per update slab (64 rows + ragged edge)
 constexpr int kMaxColBlocksPerWave = 3;   // 17 column blocks over 8 waves
 
+// Plan flags
+constexpr int kFlagRobustSolve = 1;   // skip the speculative tile solve
+constexpr int kFlagF32Updates = 2;    // tile updates on FP32 MFMA (the precision form's solves)
+
 // Task encoding for the persistent scheduler (one 64-bit word):
 //   bits  0..1   kind (0 = solve, 1 = column update, 2 = row update)
 //   bits  2..7   slab

@@ -849,7 +849,7 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         const DevView vY = dev_view(Y, P.ldc, mr, nc);
         int done = 0;
         // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
-        if (!(P.flags & 1) && *P.gmax < 0x1p1016)
+        if (!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016)
             done = uniform(tile_solve_fast(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));
         TRSYL_STAMP(stamp, 2);
         if (!done) {

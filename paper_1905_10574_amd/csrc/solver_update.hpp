@@ -23,10 +23,41 @@ constexpr int kUS = 146;
 constexpr int kUK = 16;               // k per stage
 
 struct UpdateLds {
-    double As[2][kUK][kUS];           // Aop(m, k) of the pass rows, k-major
-    double Bs[2][kUK][kUS];           // Bop(k, n) of the pass columns, k-major
+    // operand stages, viewed as T As[2][kUK][kUS] followed by T Bs[2][kUK][kUS] (T = double, or
+    // float for the FP32 form): Aop(m, k) of the pass rows and Bop(k, n) of the pass columns,
+    // k-major
+    double stage[2 * 2 * kUK * kUS];
     double rs[kWaves][kMaxTile + 3];  // per-wave partial absolute row sums of the slab
     double red[kWaves];
+};
+template <class T> __device__ __forceinline__ T *stage_A(UpdateLds &L, int buf)
+{
+    return reinterpret_cast<T *>(L.stage) + (size_t)buf * kUK * kUS;
+}
+template <class T> __device__ __forceinline__ T *stage_B(UpdateLds &L, int buf)
+{
+    return reinterpret_cast<T *>(L.stage) + (size_t)(2 + buf) * kUK * kUS;
+}
+
+// MFMA accumulator and product per element type.  The FP64 16x16x4 product leaves result element
+// t of lane l in row (l >> 4) + 4t of the (transposed) block, the FP32 one in row 4 (l >> 4) + t;
+// both in column l & 15.
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ d4 zero() { return zero4(); }
+    static __device__ __forceinline__ d4 mac(double b, double a, d4 c) { return mfma16(b, a, c); }
+    static __device__ __forceinline__ int col(int q, int t) { return q + 4 * t; }
+};
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <> struct Mfma<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ f4 zero() { return (f4){0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ f4 mac(float b, float a, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int col(int q, int t) { return 4 * q + t; }
 };
 
 __device__ __forceinline__ double wave_max(double v)
@@ -152,21 +183,23 @@ __device__ __forceinline__ void stage_load(StageRegs<SA, SB> &R, const double *A
     }
 }
 
-template <bool SA, bool SB>
+template <class T, bool SA, bool SB>
 __device__ __forceinline__ void stage_store(const StageRegs<SA, SB> &R, UpdateLds &L, int buf,
                                             int shA, int shB)
 {
+    T *As = stage_A<T>(L, buf), *Bs = stage_B<T>(L, buf);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         const int e = threadIdx.x + kThreads * i;
         if (i == 4 && threadIdx.x >= kUK * 144 - 4 * kThreads) break;
-        L.As[buf][e / 144][e % 144] = shA ? ldexp(R.a[i], shA) : R.a[i];
-        L.Bs[buf][e & 15][e >> 4] = shB ? ldexp(R.b[i], shB) : R.b[i];
+        As[(e / 144) * kUS + e % 144] = (T)(shA ? ldexp(R.a[i], shA) : R.a[i]);
+        Bs[(e & 15) * kUS + (e >> 4)] = (T)(shB ? ldexp(R.b[i], shB) : R.b[i]);
     }
 }
 
 // Target block (brow, bcol) of a pass, in the MFMA result layout: lane (r, q) holds rows
 // m0 + 16 brow + r and columns n0 + 16 bcol + q + 4i.  Loads use clamped in-range addresses.
+template <class T>
 __device__ __forceinline__ void load_target(double (&cv)[4], const DevView &Ct, int64_t ldc, int m0,
                                             int Mp, int n0, int Np, int brow, int bcol)
 {
@@ -175,7 +208,7 @@ __device__ __forceinline__ void load_target(double (&cv)[4], const DevView &Ct, 
     const int mmc = mm < m0 + Mp ? mm : m0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int nn = n0 + 16 * bcol + q + 4 * i;
+        const int nn = n0 + 16 * bcol + Mfma<T>::col(q, i);
         const int nnc = nn < n0 + Np ? nn : n0;
         cv[i] = ld_dev(Ct, (int64_t)nnc * ldc + mmc);
     }
@@ -183,9 +216,11 @@ __device__ __forceinline__ void load_target(double (&cv)[4], const DevView &Ct, 
 
 // D = 2^shC C - acc on the valid entries of the block, stored at device scope; the block's
 // absolute row sums are added to rs[row - rbase] (row tile-relative).
-__device__ __forceinline__ void store_target(const double (&cv)[4], const d4 &ac, int shC, const DevView &Ct,
-                                             int64_t ldc, int m0, int Mp, int n0, int Np, int brow,
-                                             int bcol, double *rs, int rbase)
+template <class T>
+__device__ __forceinline__ void store_target(const double (&cv)[4], const typename Mfma<T>::acc_t &ac,
+                                             int shC, int shP, const DevView &Ct, int64_t ldc, int m0,
+                                             int Mp, int n0, int Np, int brow, int bcol, double *rs,
+                                             int rbase)
 {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int mm = m0 + 16 * brow + r;
@@ -193,10 +228,11 @@ __device__ __forceinline__ void store_target(const double (&cv)[4], const d4 &ac
     double rsum = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int nn = n0 + 16 * bcol + q + 4 * i;
+        const int nn = n0 + 16 * bcol + Mfma<T>::col(q, i);
         if (mok && nn < n0 + Np) {
             const double c = shC ? ldexp(cv[i], shC) : cv[i];
-            const double d = c - ac[i];
+            const double p = shP ? ldexp((double)ac[i], shP) : (double)ac[i];
+            const double d = c - p;
             st_dev(Ct, (int64_t)nn * ldc + mm, d);
             rsum += fabs(d);
         }
@@ -216,12 +252,17 @@ __device__ __forceinline__ void store_target(const double (&cv)[4], const d4 &ac
 // blocks), all accumulated with v_mfma_f64_16x16x4 from LDS stages of 16 k that are double
 // buffered: the next stage's global loads are in flight while the current stage's MFMAs run.
 // ---------------------------------------------------------------------------------------------
-template <bool COL>
+// T = double: operands staged as they are (times 2^shA, 2^shB), product used as computed (shP
+// = 0).  T = float: operands staged times 2^shA, 2^shB chosen to normalise them into FP32's range,
+// product taken back by 2^shP; every scale is an exact power of two.
+template <bool COL, class T>
 __device__ __forceinline__ void update_passes(const Plan &P, const double *Aop, int64_t lda,
                                               const double *Bop, int64_t ldb, int K, int shA,
-                                              int shB, int shC, double *Ct, int rows, int cols,
-                                              int rb_lo, int nrb, UpdateLds &L, uint64_t *ustamp)
+                                              int shB, int shP, int shC, double *Ct, int rows,
+                                              int cols, int rb_lo, int nrb, UpdateLds &L,
+                                              uint64_t *ustamp)
 {
+    typedef typename Mfma<T>::acc_t acc_t;
     constexpr bool SA = !COL, SB = COL;     // the solved tile Y_S is the shared operand
     const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
@@ -252,40 +293,41 @@ __device__ __forceinline__ void update_passes(const Plan &P, const double *Aop, 
                 xc[j] = e < xrow ? e : 8;
                 if (e < nx) nxw = j + 1;
             }
-            d4 acc[4][2], accx[3];
+            acc_t acc[4][2], accx[3];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) { acc[a][0] = zero4(); acc[a][1] = zero4(); }
+            for (int a = 0; a < 4; ++a) { acc[a][0] = Mfma<T>::zero(); acc[a][1] = Mfma<T>::zero(); }
 #pragma unroll
-            for (int j = 0; j < 3; ++j) accx[j] = zero4();
+            for (int j = 0; j < 3; ++j) accx[j] = Mfma<T>::zero();
 
             StageRegs<SA, SB> SR;
             stage_load<SA, SB>(SR, Aop, vA, lda, m0, Mp, Bop, vB, ldb, n0, Np, 0, K);
-            stage_store<SA, SB>(SR, L, 0, shA, shB);
+            stage_store<T, SA, SB>(SR, L, 0, shA, shB);
             __syncthreads();
             if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[2] = wall_clock64();
             for (int c = 0; c < nkc; ++c) {
                 const int buf = c & 1;
                 const bool more = c + 1 < nkc;
                 if (more) stage_load<SA, SB>(SR, Aop, vA, lda, m0, Mp, Bop, vB, ldb, n0, Np, kUK * (c + 1), K);
+                const T *As = stage_A<T>(L, buf), *Bs = stage_B<T>(L, buf);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int k = 4 * q + j;
-                    double av[4], bv[2];
+                    T av[4], bv[2];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) av[a] = L.As[buf][k][16 * (4 * wr + a) + r];
+                    for (int a = 0; a < 4; ++a) av[a] = As[k * kUS + 16 * (4 * wr + a) + r];
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) bv[b] = L.Bs[buf][k][16 * (2 * wc + b) + r];
+                    for (int b = 0; b < 2; ++b) bv[b] = Bs[k * kUS + 16 * (2 * wc + b) + r];
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
 #pragma unroll
                         for (int b = 0; b < 2; ++b)
-                            if (a < nrm && b < ncm) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+                            if (a < nrm && b < ncm) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
 #pragma unroll
                     for (int x = 0; x < 3; ++x)
                         if (x < nxw)
-                            accx[x] = mfma16(L.Bs[buf][k][16 * xc[x] + r], L.As[buf][k][16 * xr[x] + r], accx[x]);
+                            accx[x] = Mfma<T>::mac(Bs[k * kUS + 16 * xc[x] + r], As[k * kUS + 16 * xr[x] + r], accx[x]);
                 }
-                if (more) stage_store<SA, SB>(SR, L, buf ^ 1, shA, shB);
+                if (more) stage_store<T, SA, SB>(SR, L, buf ^ 1, shA, shB);
                 __syncthreads();
             }
 
@@ -296,21 +338,21 @@ __device__ __forceinline__ void update_passes(const Plan &P, const double *Aop, 
                 double cm[4][4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
-                    if (a < nrm && b < ncm) load_target(cm[a], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
+                    if (a < nrm && b < ncm) load_target<T>(cm[a], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
                     if (a < nrm && b < ncm)
-                        store_target(cm[a], acc[a][b], shC, vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a,
-                                     2 * wc + b, L.rs[w], 16 * rb_lo);
+                        store_target<T>(cm[a], acc[a][b], shC, shP, vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a,
+                                        2 * wc + b, L.rs[w], 16 * rb_lo);
             }
             double cx[3][4];
 #pragma unroll
             for (int x = 0; x < 3; ++x)
-                if (x < nxw) load_target(cx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
+                if (x < nxw) load_target<T>(cx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
 #pragma unroll
             for (int x = 0; x < 3; ++x)
                 if (x < nxw)
-                    store_target(cx[x], accx[x], shC, vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x], L.rs[w], 16 * rb_lo);
+                    store_target<T>(cx[x], accx[x], shC, shP, vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x], L.rs[w], 16 * rb_lo);
         }
     }
 }
@@ -362,14 +404,25 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
     if (ustamp && threadIdx.x == 0) ustamp[1] = wall_clock64();
 
     if (rows > 0 && cols > 0 && nrb > 0 && K > 0) {
-        if (colu) {
-            const int k0 = uniform(P.rowoff[si]);
-            update_passes<true>(P, P.A + (int64_t)k0 * P.lda + r0, P.lda, P.C + (int64_t)c0 * P.ldc + k0,
-                                P.ldc, K, 0, shY, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
+        const int k0 = colu ? uniform(P.rowoff[si]) : uniform(P.coloff[sl]);
+        const double *Aop = colu ? P.A + (int64_t)k0 * P.lda + r0 : P.C + (int64_t)k0 * P.ldc + r0;
+        const double *Bop = colu ? P.C + (int64_t)c0 * P.ldc + k0 : P.B + (int64_t)c0 * P.ldb + k0;
+        const int64_t lda_ = colu ? P.lda : P.ldc, ldb_ = colu ? P.ldc : P.ldb;
+        if (P.flags & kFlagF32Updates) {
+            // normalise both operands to entries below 1 (their infinity norms bound every entry)
+            // and take the product back by the shifts plus the update's scale of Y_S
+            const int sT = tn > 0.0 ? -(ilogb(tn) + 1) : 0;
+            const int sY = yn > 0.0 ? -(ilogb(yn) + 1) : 0;
+            const int shP = uniform(shY - sT - sY);
+            if (colu)
+                update_passes<true, float>(P, Aop, lda_, Bop, ldb_, K, sT, sY, shP, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
+            else
+                update_passes<false, float>(P, Aop, lda_, Bop, ldb_, K, sY, sT, shP, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
         } else {
-            const int k0 = uniform(P.coloff[sl]);
-            update_passes<false>(P, P.C + (int64_t)k0 * P.ldc + r0, P.ldc, P.B + (int64_t)c0 * P.ldb + k0,
-                                 P.ldb, K, shY, 0, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
+            if (colu)
+                update_passes<true, double>(P, Aop, lda_, Bop, ldb_, K, 0, shY, 0, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
+            else
+                update_passes<false, double>(P, Aop, lda_, Bop, ldb_, K, shY, 0, 0, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
         }
     } else if (rows > 0 && cols > 0 && nrb > 0 && shC != 0) {
         // an empty source still rescales the target to the common exponent

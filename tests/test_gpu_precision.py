@@ -1,0 +1,45 @@
+"""GPU tests of the precision form (FP32-MFMA tile updates, FP64 tile solves / bounds / residual,
+FP64 refinement sweeps): eq. (9) after the sweeps and agreement with the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import trsyl_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1905_10574_amd as T
+    T.lib()
+    return T
+
+
+@pytest.mark.parametrize("m,n,tile,sweeps", [(64, 64, 32, 2), (300, 257, 64, 2), (513, 260, 128, 3),
+                                             (1000, 700, 128, 2)])
+def test_fp32_refine_separated(T, m, n, tile, sweeps):
+    A, B, C = W.separated_problem(m + n, m, n)
+    Y, e, info = T.solve(A, B, C, tile=tile, precision="fp32_refine", max_sweeps=sweeps)
+    assert info == 0 and e == 0
+    res = T.residual(A, B, Y, e, C)
+    assert res <= 1e-12, res
+    Yo, eo, _ = oracle.drsylv(A, B, C, 64, threads=8)
+    Y = Y.cpu().numpy()
+    err = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
+    assert err <= 1e-10, err
+
+
+def test_fp32_refine_growth(T):
+    """Growth input: the FP32-update solves stay robust (alpha < 1, finite, bounded) and the
+    refined pair satisfies eq. (9)."""
+    A, B, C = W.growth_problem(1, 200, 180)
+    Y, e, info = T.solve(A, B, C, tile=64, precision="fp32_refine", max_sweeps=3)
+    assert e > 0 and info in (0, 1)
+    Yn = Y.cpu().numpy()
+    assert np.all(np.isfinite(Yn)) and np.abs(Yn).max() <= 2.0 ** 1022
+    assert T.residual(A, B, Y, e, C) <= 1e-12
