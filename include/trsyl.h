@@ -128,18 +128,27 @@ int trsyl_grad(int64_t m, int64_t n, const double *A, int64_t lda, const double 
                int64_t lddc, trsyl_stream_t stream);
 
 /*
- * Batched robust solve: `count` independent problems of arbitrary sizes in one persistent
- * launch.  Pointer arrays live in device memory; m, n, lda, ldb, ldc are host arrays.
- * scale_log2, scale, info are device arrays of length count.  The return value is the host
- * argument check only; per-problem status goes to info[i].
+ * Batched robust solve: `count` independent problems of arbitrary sizes (rectangular allowed) in
+ * one launch per stage -- structure, bounds, one persistent tile-DAG kernel over the merged task
+ * lists of all problems, finalisation and consistency scaling (the forward FP64 form, Algorithm 4
+ * per problem).
+ *   m, n, lda, ldb, ldc   host arrays [count]
+ *   A, B, C               host arrays [count] of device pointers (as in trsyl_robust)
+ *   tiles                 host array [2 * count] of (tile_m, tile_n) per problem, e.g. from an
+ *                         autotuner; NULL = opts->tile_m / tile_n for every problem
+ *   scale_log2, scale, info   device arrays [count] (scale may be NULL)
+ *   workspace             >= trsyl_batched_workspace_size(count, m, n, tiles, opts), 256-aligned
+ * A problem's results are identical to trsyl_robust's with the same tile sizes.  The return value
+ * is the host argument check only (negative: argument index); per-problem status goes to info[i].
  */
 size_t trsyl_batched_workspace_size(int32_t count, const int64_t *m, const int64_t *n,
-                                    const trsyl_opts *opts);
+                                    const int32_t *tiles, const trsyl_opts *opts);
 int trsyl_robust_batched(int32_t count, const int64_t *m, const int64_t *n,
                          const double *const *A, const int64_t *lda, const double *const *B,
                          const int64_t *ldb, double *const *C, const int64_t *ldc,
-                         int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
-                         void *workspace, size_t ws_bytes, trsyl_stream_t stream);
+                         const int32_t *tiles, int64_t *scale_log2, double *scale, int32_t *info,
+                         const trsyl_opts *opts, void *workspace, size_t ws_bytes,
+                         trsyl_stream_t stream);
 
 /*
  * Relative residual of eq. (9), evaluated on the device in FP64 with power-of-two

@@ -13,6 +13,7 @@ import os
 import torch
 
 __all__ = ["Opts", "lib", "solve", "solve_async", "adjoint", "adjoint_async", "grad", "residual", "trsyl",
+           "solve_batched", "solve_batched_async", "autotune_tiles",
            "debug_protect_update", "debug_protect_division", "TrsylFunction", "workspace_size",
            "FP64", "FP32_REFINE", "SCHED_DAG", "SCHED_FRONTS"]
 
@@ -66,9 +67,9 @@ def lib() -> ctypes.CDLL:
         L.trsyl_residual.argtypes = [_I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _I64, _P, _P,
                                      ctypes.c_size_t, _P]
         L.trsyl_residual.restype = ctypes.c_int
-        L.trsyl_batched_workspace_size.argtypes = [ctypes.c_int32, _P, _P, ctypes.POINTER(Opts)]
+        L.trsyl_batched_workspace_size.argtypes = [ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts)]
         L.trsyl_batched_workspace_size.restype = ctypes.c_size_t
-        L.trsyl_robust_batched.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+        L.trsyl_robust_batched.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                            ctypes.POINTER(Opts), _P, ctypes.c_size_t, _P]
         L.trsyl_robust_batched.restype = ctypes.c_int
         L.trsyl_debug_protect_update.argtypes = [ctypes.c_int32, _P, _P, _P]
@@ -282,3 +283,118 @@ class TrsylFunction(torch.autograd.Function):
 def trsyl(A, B, C, tile=None):
     """Differentiable robust solve: returns (Y, e) with A Y + Y B = 2^-e C."""
     return TrsylFunction.apply(A, B, C, tile)
+
+
+def solve_batched_async(As, Bs, Cs, tiles=None, opts: Opts | None = None):
+    """Enqueue one batched robust solve of len(As) independent problems on the current stream.
+    tiles: None (opts' tile for all), "auto" (the autotuner's table), or a list of (tile_m, tile_n).
+    Returns (Ys, e, info): Ys the column-major storages (Y_i = Ys[i].t()), e / info device tensors."""
+    opts = opts or make_opts()
+    count = len(As)
+    Acs = [colmajor(A) for A in As]
+    dev = Acs[0].device if count else torch.device("cuda")
+    Bcs = [colmajor(B, dev) for B in Bs]
+    Ycs = [colmajor(C, dev) for C in Cs]
+    ms = [Y.shape[1] for Y in Ycs]
+    ns = [Y.shape[0] for Y in Ycs]
+    if isinstance(tiles, str) and tiles == "auto":
+        tiles = [(tile_for(mi), tile_for(ni)) for mi, ni in zip(ms, ns)]
+    I64 = ctypes.c_int64 * count
+    m_a, n_a = I64(*ms), I64(*ns)
+    lda, ldb = I64(*[max(1, x) for x in ms]), I64(*[max(1, x) for x in ns])
+    ldc = I64(*[max(1, x) for x in ms])
+    Pa = ctypes.c_void_p * count
+    A_p, B_p, C_p = Pa(*[a.data_ptr() for a in Acs]), Pa(*[b.data_ptr() for b in Bcs]), Pa(*[y.data_ptr() for y in Ycs])
+    t_a = None
+    if tiles is not None:
+        t_a = (ctypes.c_int32 * (2 * count))(*[int(v) for tt in tiles for v in tt])
+    e = torch.zeros(max(count, 1), dtype=torch.int64, device=dev)
+    sc = torch.zeros(max(count, 1), dtype=torch.float64, device=dev)
+    info = torch.zeros(max(count, 1), dtype=torch.int32, device=dev)
+    L = lib()
+    need = int(L.trsyl_batched_workspace_size(count, m_a, n_a, t_a, ctypes.byref(opts)))
+    if need == 0 and count > 0:
+        raise RuntimeError("trsyl_batched_workspace_size rejected the arguments")
+    ws_keep, ws_ptr = _aligned_workspace(max(need, 256), dev)
+    rc = L.trsyl_robust_batched(count, m_a, n_a, A_p, lda, B_p, ldb, C_p, ldc, t_a, e.data_ptr(),
+                                sc.data_ptr(), info.data_ptr(), ctypes.byref(opts), ws_ptr, need,
+                                _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_robust_batched rejected its arguments: {rc}")
+    solve_batched_async._keep = (Acs, Bcs, ws_keep, m_a, n_a, A_p, B_p, C_p, t_a)
+    return Ycs, e, info
+
+
+def solve_batched(As, Bs, Cs, tiles=None, **kw):
+    """Batched robust solve; returns a list of (Y, e, info)."""
+    Ycs, e, info = solve_batched_async(As, Bs, Cs, tiles, make_opts(**kw))
+    if Ycs:
+        torch.cuda.synchronize(Ycs[0].device)
+    es, infos = e.cpu().tolist(), info.cpu().tolist()
+    return [(Y.t(), es[i], infos[i]) for i, Y in enumerate(Ycs)]
+
+
+# ---------------------------------------------------------------------------------------------
+# Tile autotuner for batched solves.  For each size bucket (powers of two), a batch of synthetic
+# problems of that size (upper triangular, diagonal U[1,10], strictly upper N(0,1)/sqrt(n), C
+# N(0,1)) is solved with every candidate tile; the tile with the highest throughput wins.  The
+# table lives in memory for the process.
+# ---------------------------------------------------------------------------------------------
+_TILE_TABLE: dict[int, int] = {}
+TILE_CANDIDATES = (16, 32, 48, 64, 96, 128)
+BUCKETS = (64, 128, 256, 512, 1024, 2048)
+
+
+def _bucket(x: int) -> int:
+    best = BUCKETS[0]
+    for b in BUCKETS:
+        if abs(b - x) < abs(best - x) or (x > b):
+            best = b
+    return best
+
+
+def tile_for(x: int) -> int:
+    """Autotuned tile for a dimension of size x: the entry of the nearest tuned bucket (by ratio);
+    before autotune_tiles ran, 128 (or x itself for small x, at least 16)."""
+    if not _TILE_TABLE:
+        return 128 if x >= 128 else max(16, min(128, x))
+    import math
+    lx = math.log(max(1, x))
+    b = min(_TILE_TABLE, key=lambda k: (abs(math.log(k) - lx), k))
+    return _TILE_TABLE[b]
+
+
+def autotune_tiles(buckets=BUCKETS, candidates=TILE_CANDIDATES, batch_flops=2e10, reps=2, seed=0,
+                   device=None) -> dict[int, int]:
+    """Measure and store the best tile per size bucket; returns the table."""
+    device = device or torch.device("cuda")
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    for s in buckets:
+        count = int(max(1, min(64, batch_flops // (2.0 * s ** 3))))
+        As, Bs, Cs = [], [], []
+        for _ in range(count):
+            A = torch.triu(torch.randn(s, s, generator=gen, dtype=torch.float64), 1) / s ** 0.5
+            A += torch.diag(torch.rand(s, generator=gen, dtype=torch.float64) * 9 + 1)
+            B = torch.triu(torch.randn(s, s, generator=gen, dtype=torch.float64), 1) / s ** 0.5
+            B += torch.diag(torch.rand(s, generator=gen, dtype=torch.float64) * 9 + 1)
+            As.append(A.to(device)); Bs.append(B.to(device))
+            Cs.append(torch.randn(s, s, generator=gen, dtype=torch.float64).to(device))
+        best, best_t = None, None
+        for t in candidates:
+            if t > max(16, s):
+                continue
+            opts = make_opts(tile=t)
+            times = []
+            for _ in range(reps + 1):
+                torch.cuda.synchronize(device)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                solve_batched_async(As, Bs, Cs, [(t, t)] * count, opts)
+                ev1.record()
+                torch.cuda.synchronize(device)
+                times.append(ev0.elapsed_time(ev1))
+            tm = min(times[1:])
+            if best is None or tm < best:
+                best, best_t = tm, t
+        _TILE_TABLE[s] = best_t
+    return dict(_TILE_TABLE)

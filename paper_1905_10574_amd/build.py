@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libtrsyl.so")
 ARCH = os.environ.get("TRSYL_ARCH", "gfx950")
 
 HIP_SOURCES = ["solver.hip", "refine.hip", "extras.hip"]
-HOST_SOURCES = ["capi.cpp", "capi_extras.cpp", "capi_batched.cpp"]
+HOST_SOURCES = ["capi.cpp", "capi_extras.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 # packed FP32 VALU forms are disabled for all device code
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

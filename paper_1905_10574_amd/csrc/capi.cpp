@@ -371,6 +371,118 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
     return 0;
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// Batched solves.  Workspace: plans, stage offset tables and the ticket; then one region per
+// problem (its layout up to the zeroed state); then the shared per-worker scratch; then the merged
+// task list and the problem index of every task.
+// ---------------------------------------------------------------------------------------------
+struct BLayout {
+    int count = 0, workers = 0;
+    std::vector<Resolved> r;
+    std::vector<Layout> L;
+    std::vector<size_t> region;           // offset of problem p's region
+    size_t plans = 0, offs = 0, ticket = 0, regions_begin = 0, regions_end = 0, scratch = 0,
+           tasks = 0, tprob = 0, total = 0;
+    int64_t ntasks = 0;
+};
+
+// Returns 0 or the negative argument index that is invalid.
+int make_blayout(int32_t count, const int64_t *m, const int64_t *n, const int32_t *tiles,
+                 const trsyl_opts *opts, BLayout *B)
+{
+    B->count = count;
+    B->r.resize(count);
+    B->L.resize(count);
+    B->region.resize(count);
+    Resolved base;
+    if (int e = resolve(opts, &base, 14)) return e;
+    if (base.precision != TRSYL_FP64) return -14;    // batched solves run the FP64 form
+    B->workers = base.workers ? base.workers : device_cus();
+    size_t o = 0;
+    B->plans = o; o = align_up(o + sizeof(Plan) * (size_t)count);
+    B->offs = o; o = align_up(o + 4 * 5 * (size_t)(count + 1));
+    B->ticket = o; o = align_up(o + 4);
+    B->regions_begin = o;
+    for (int p = 0; p < count; ++p) {
+        if (m[p] < 0 || n[p] < 0 || m[p] > (int64_t)INT32_MAX / 2 || n[p] > (int64_t)INT32_MAX / 2) return -2;
+        trsyl_opts op;
+        if (opts) op = *opts; else trsyl_default_opts(&op);
+        if (tiles) { op.tile_m = tiles[2 * p]; op.tile_n = tiles[2 * p + 1]; }
+        if (int e = resolve(&op, &B->r[p], 10)) return e;
+        B->r[p].precision = TRSYL_FP64;
+        B->r[p].scheduler = TRSYL_SCHED_DAG;
+        Resolved rr = B->r[p];
+        rr.workers = B->workers;
+        B->L[p] = make_layout(std::max<int64_t>(m[p], 1), std::max<int64_t>(n[p], 1), rr);
+        if (m[p] == 0 || n[p] == 0) { B->L[p].pt = 0; B->L[p].qt = 0; }
+        B->region[p] = o;
+        o = align_up(o + B->L[p].zero_end);
+        B->ntasks += (B->L[p].pt && B->L[p].qt) ? count_tasks(B->L[p].pt, B->L[p].qt, B->r[p].slabs) : 0;
+    }
+    B->regions_end = o;
+    B->scratch = o; o = align_up(o + 8 * (size_t)B->workers * kMaxTile * kMaxTile);
+    B->tasks = o; o = align_up(o + 8 * (size_t)B->ntasks);
+    B->tprob = o; o = align_up(o + 4 * (size_t)B->ntasks);
+    B->total = o;
+    return 0;
+}
+
+// Merged task order: every problem's own topological order (from its list-scheduling
+// simulation), interleaved by fractional progress -- the next task is the one whose position in
+// its problem's list, divided by that list's length, is smallest (larger problems first on ties).
+struct MergedTasks {
+    uint64_t *pinned = nullptr;   // tasks, then the uint32 problem indices
+    int64_t n = 0;
+};
+const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t *n)
+{
+    static std::mutex mu;
+    static std::map<std::vector<int64_t>, MergedTasks *> cache;
+    std::vector<int64_t> key;
+    key.push_back(B.workers);
+    for (int p = 0; p < B.count; ++p) {
+        key.push_back(B.L[p].pt); key.push_back(B.L[p].qt); key.push_back(B.r[p].slabs);
+        key.push_back(m[p] * n[p] * (m[p] + n[p]));
+    }
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    std::vector<const TaskCache *> lists(B.count, nullptr);
+    for (int p = 0; p < B.count; ++p) {
+        if (B.L[p].pt && B.L[p].qt) {
+            lists[p] = get_tasks(B.L[p].pt, B.L[p].qt, B.r[p].slabs, B.workers);
+            if (!lists[p]) return nullptr;
+        }
+    }
+    typedef std::tuple<double, int64_t, int> Key;    // (fraction, -flops, problem)
+    std::priority_queue<Key, std::vector<Key>, std::greater<Key>> q;
+    std::vector<size_t> pos(B.count, 0);
+    auto push = [&](int p) {
+        const size_t len = lists[p]->tasks.size();
+        if (pos[p] < len) q.emplace((double)(pos[p] + 1) / (double)len, -(m[p] * n[p] * (m[p] + n[p])), p);
+    };
+    for (int p = 0; p < B.count; ++p) if (lists[p]) push(p);
+    MergedTasks *mt = new MergedTasks;
+    mt->n = B.ntasks;
+    const size_t bytes = 12 * (size_t)B.ntasks + 8;
+    if (hipHostMalloc((void **)&mt->pinned, bytes, hipHostMallocDefault) != hipSuccess) { delete mt; return nullptr; }
+    uint32_t *prob = (uint32_t *)(mt->pinned + B.ntasks);
+    int64_t k = 0;
+    while (!q.empty()) {
+        const int p = std::get<2>(q.top());
+        q.pop();
+        mt->pinned[k] = lists[p]->tasks[pos[p]];
+        prob[k] = (uint32_t)p;
+        ++k;
+        ++pos[p];
+        push(p);
+    }
+    if (k != B.ntasks) { hipHostFree(mt->pinned); delete mt; return nullptr; }
+    cache[key] = mt;
+    return mt;
+}
+
 }  // namespace
 
 extern "C" {
@@ -441,6 +553,110 @@ int trsyl_debug_protect_division(int32_t count, const double *in, int32_t *out, 
     if (count < 0) return -1;
     if (count > 0 && (bad_ptr(in) || bad_ptr(out))) return -2;
     return launch_debug_protect(1, count, in, out, (hipStream_t)s) == hipSuccess ? 0 : -100;
+}
+
+
+size_t trsyl_batched_workspace_size(int32_t count, const int64_t *m, const int64_t *n, const int32_t *tiles,
+                                    const trsyl_opts *opts)
+{
+    if (count < 0 || (count > 0 && (!m || !n))) return 0;
+    BLayout B;
+    if (make_blayout(count, m, n, tiles, opts, &B)) return 0;
+    return B.total;
+}
+
+int trsyl_robust_batched(int32_t count, const int64_t *m, const int64_t *n, const double *const *A,
+                         const int64_t *lda, const double *const *B, const int64_t *ldb, double *const *C,
+                         const int64_t *ldc, const int32_t *tiles, int64_t *scale_log2, double *scale,
+                         int32_t *info, const trsyl_opts *opts, void *workspace, size_t ws_bytes,
+                         trsyl_stream_t stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (count < 0) return -1;
+    if (count == 0) return 0;
+    if (!m || !n) return -2;
+    if (!A || !lda) return -4;
+    if (!B || !ldb) return -6;
+    if (!C || !ldc) return -8;
+    if (bad_ptr(scale_log2)) return -11;
+    if (bad_ptr(info)) return -13;
+    for (int p = 0; p < count; ++p) {
+        if (m[p] < 0 || n[p] < 0) return -2;
+        if (m[p] > 0 && bad_ptr(A[p])) return -4;
+        if (lda[p] < std::max<int64_t>(1, m[p])) return -5;
+        if (n[p] > 0 && bad_ptr(B[p])) return -6;
+        if (ldb[p] < std::max<int64_t>(1, n[p])) return -7;
+        if (m[p] > 0 && n[p] > 0 && bad_ptr(C[p])) return -8;
+        if (ldc[p] < std::max<int64_t>(1, m[p])) return -9;
+    }
+    BLayout BL;
+    if (int e = make_blayout(count, m, n, tiles, opts, &BL)) return e;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -15;
+    if (ws_bytes < BL.total) return -16;
+    char *ws = (char *)workspace;
+    // host images of the plans and the stage offset tables
+    std::vector<Plan> plans(count);
+    std::vector<int32_t> offs(5 * (size_t)(count + 1), 0);
+    int32_t *oS = offs.data(), *oA = oS + (count + 1), *oB = oA + (count + 1), *oC = oB + (count + 1),
+            *oK = oC + (count + 1);
+    for (int p = 0; p < count; ++p) {
+        const Layout &L = BL.L[p];
+        Plan P = make_plan(m[p], n[p], A[p], lda[p], B[p], ldb[p], C[p], ldc[p], BL.r[p], L, ws + BL.region[p]);
+        P.pt = L.pt; P.qt = L.qt;
+        P.tasks = nullptr; P.ntasks = 0;
+        P.scratch = (double *)(ws + BL.scratch);
+        P.ticket = (uint32_t *)(ws + BL.ticket);
+        P.e_out = scale_log2 + p;
+        P.scale_out = scale ? scale + p : nullptr;
+        P.info_out = info + p;
+        P.trace = nullptr;
+        plans[p] = P;
+        const int64_t items = std::max(m[p], n[p]) + 2;
+        const int gS = (L.pt && L.qt) ? (int)std::min<int64_t>((items + 255) / 256, 64) : 0;
+        oS[p + 1] = oS[p] + gS;
+        oA[p + 1] = oA[p] + ((L.pt && L.qt) ? L.pt * L.pt : 0);
+        oB[p + 1] = oB[p] + ((L.pt && L.qt) ? L.qt * L.qt : 0);
+        oC[p + 1] = oC[p] + L.pt * L.qt;
+        oK[p + 1] = oK[p] + ((L.pt && L.qt) ? consistency_per_tile(BL.r[p].tm, BL.r[p].tn) * L.pt * L.qt : 0);
+    }
+    const MergedTasks *mt = get_merged(BL, m, n);
+    if (!mt) return -100;
+    if (launch_fill_zero(ws + BL.ticket, BL.regions_end - BL.ticket, stream) != hipSuccess) return -100;
+    if (hipMemcpyAsync(ws + BL.plans, plans.data(), sizeof(Plan) * (size_t)count, hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+        return -100;
+    if (hipMemcpyAsync(ws + BL.offs, offs.data(), 4 * offs.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return -100;
+    if (BL.ntasks > 0) {
+        if (hipMemcpyAsync(ws + BL.tasks, mt->pinned, 8 * (size_t)BL.ntasks, hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(ws + BL.tprob, mt->pinned + BL.ntasks, 4 * (size_t)BL.ntasks, hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return -100;
+    }
+    BatchedLaunch bl{};
+    bl.count = count;
+    bl.plans = (const Plan *)(ws + BL.plans);
+    const int32_t *dof = (const int32_t *)(ws + BL.offs);
+    bl.off_structure = dof;
+    bl.off_A = dof + (count + 1);
+    bl.off_B = dof + 2 * (count + 1);
+    bl.off_C = dof + 3 * (count + 1);
+    bl.off_consistency = dof + 4 * (count + 1);
+    bl.blocks_structure = oS[count];
+    bl.blocks_bounds = oA[count] + oB[count] + oC[count];
+    bl.blocks_consistency = oK[count];
+    bl.tasks = (const uint64_t *)(ws + BL.tasks);
+    bl.tprob = (const uint32_t *)(ws + BL.tprob);
+    bl.ntasks = BL.ntasks;
+    bl.ticket = (uint32_t *)(ws + BL.ticket);
+    bl.scratch = (double *)(ws + BL.scratch);
+    bl.workers = BL.workers;
+    hipEvent_t *ev = opts ? (hipEvent_t *)opts->profile_events : nullptr;
+    if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
+    if (launch_batched(bl, stream) != hipSuccess) return -100;
+    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
+    return 0;
 }
 
 }  // extern "C"

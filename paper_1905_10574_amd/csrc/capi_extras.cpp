@@ -1,6 +1,5 @@
-// Entry points of include/trsyl.h beside the forward solve: the adjoint solve, the gradient
-// products and the eq. (9) residual.  The batched driver is in capi_batched.cpp and the
-// precision form in capi_refine.cpp.
+// Entry points of include/trsyl.h beside the forward, precision-form and batched solves (those
+// are in capi.cpp): the adjoint solve, the gradient products and the eq. (9) residual.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -103,6 +103,13 @@ __device__ __forceinline__ Plan uniform_plan(const Plan &in)
     return P;
 }
 
+// blocks per tile of the consistency pass
+__host__ __device__ inline int consistency_per_tile(int tm, int tn)
+{
+    const int per = (tm * tn + kThreads - 1) / kThreads;
+    return per < 8 ? per : 8;
+}
+
 __host__ __device__ inline int tile_updates(const Plan &P, int T)
 {
     const int i = T / P.qt, l = T % P.qt;

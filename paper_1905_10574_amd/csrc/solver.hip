@@ -20,10 +20,10 @@ namespace trsyl {
 // ---------------------------------------------------------------------------------------------
 // Structure and tiling
 // ---------------------------------------------------------------------------------------------
-__global__ void k_structure(Plan P)
+__device__ void structure_body(const Plan &P, int64_t blk, int64_t nblk)
 {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = blk * blockDim.x + threadIdx.x;
+    const int64_t nthr = nblk * blockDim.x;
     for (int64_t i = tid; i + 2 < P.m; i += nthr)
         if (P.A[i * P.lda + i + 1] != 0.0 && P.A[(i + 1) * P.lda + i + 2] != 0.0)
             set_status(P.status, kBadStructure);
@@ -53,6 +53,7 @@ __global__ void k_structure(Plan P)
         P.coloff[k] = (int32_t)v;
     }
 }
+__global__ void k_structure(Plan P) { structure_body(P, blockIdx.x, gridDim.x); }
 
 // ||T_ik||_inf for a tile pair of the quasi-triangular matrix T (A or B); the diagonal tile also
 // feeds the global max |entry| and, for B, the 1-norm.  Entries below the first subdiagonal are
@@ -95,25 +96,25 @@ __device__ void bound_tile(const Plan &P, const double *T, int64_t ld, const int
     if (threadIdx.x == 0) out[(size_t)i * nt + k] = best;
 }
 
-__global__ void __launch_bounds__(kThreads) k_bounds_A(Plan P)
+__device__ void bounds_A_body(const Plan &P, int b)
 {
-    const int i = blockIdx.x / P.pt, k = blockIdx.x % P.pt;
+    const int i = b / P.pt, k = b % P.pt;
     if (i > k) return;
     bound_tile(P, P.A, P.lda, P.rowoff, P.pt, i, k, P.anorm, nullptr);
 }
-
-__global__ void __launch_bounds__(kThreads) k_bounds_B(Plan P)
+__device__ void bounds_B_body(const Plan &P, int b)
 {
-    const int l = blockIdx.x / P.qt, j = blockIdx.x % P.qt;
+    const int l = b / P.qt, j = b % P.qt;
     if (l > j) return;
     bound_tile(P, P.B, P.ldb, P.coloff, P.qt, l, j, P.bnorm, P.bdiag1);
 }
+__global__ void __launch_bounds__(kThreads) k_bounds_A(Plan P) { bounds_A_body(P, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_bounds_B(Plan P) { bounds_B_body(P, blockIdx.x); }
 
 // ||C_kl||_inf, input check, and version 0 of every tile's state.
-__global__ void __launch_bounds__(kThreads) k_bounds_C(Plan P)
+__device__ void bounds_C_body(const Plan &P, int T)
 {
     __shared__ double red[kWaves];
-    const int T = blockIdx.x;
     const int k = T / P.qt, l = T % P.qt;
     const int r0 = P.rowoff[k], r1 = P.rowoff[k + 1], c0 = P.coloff[l], c1 = P.coloff[l + 1];
     double best = 0.0;
@@ -136,6 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_bounds_C(Plan P)
         P.ver[T] = 0;
     }
 }
+__global__ void __launch_bounds__(kThreads) k_bounds_C(Plan P) { bounds_C_body(P, blockIdx.x); }
 
 // ---------------------------------------------------------------------------------------------
 // Persistent scheduler
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(kThreads) k_front_update(Plan Pk, int d, int k
 // ---------------------------------------------------------------------------------------------
 // alpha = min alpha_kl, i.e. e = max e_kl; then consistency scaling.
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_finalize(Plan P)
+__device__ void finalize_body(const Plan &P)
 {
     __shared__ int red[kWaves];
     int e = 0;
@@ -288,10 +290,11 @@ __global__ void __launch_bounds__(kThreads) k_finalize(Plan P)
         *P.info_out = st;
     }
 }
+__global__ void __launch_bounds__(kThreads) k_finalize(Plan P) { finalize_body(P); }
 
-__global__ void __launch_bounds__(kThreads) k_consistency(Plan P, int per_tile)
+__device__ void consistency_body(const Plan &P, int per_tile, int b)
 {
-    const int T = blockIdx.x / per_tile, part = blockIdx.x % per_tile;
+    const int T = b / per_tile, part = b % per_tile;
     const int st = *(volatile int32_t *)P.status;
     if (st >= kBadStructure) return;
     const int eT = tile_exp_at(P, T, tile_updates(P, T) + 1);
@@ -306,6 +309,119 @@ __global__ void __launch_bounds__(kThreads) k_consistency(Plan P, int per_tile)
         const int rr = t % mr, cc = t / mr;
         double *p = P.C + (int64_t)(c0 + cc) * P.ldc + r0 + rr;
         *p = ldexp(*p, -shi);
+    }
+}
+__global__ void __launch_bounds__(kThreads) k_consistency(Plan P, int per_tile)
+{
+    consistency_body(P, per_tile, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched solve: many problems, each with its own plan (device array), in one launch per stage.
+// A stage's blocks are split among the problems by the offsets off[0..count] (problem p owns
+// blocks off[p] .. off[p+1]-1).  The persistent scheduler takes tickets from one merged task list
+// in which every problem's tasks keep their own topological order, so the no-deadlock argument of
+// the single solve carries over; a problem with a structure or input error has its tasks skipped
+// (their counters still move).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int find_problem(const int32_t *off, int count, int b)
+{
+    int lo = 0, hi = count - 1;                    // largest p with off[p] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return uniform(lo);
+}
+
+__global__ void k_structure_b(const Plan *plans, const int32_t *off, int count)
+{
+    const int p = find_problem(off, count, blockIdx.x);
+    const Plan P = uniform_plan(plans[p]);
+    structure_body(P, blockIdx.x - uniform(off[p]), uniform(off[p + 1] - off[p]));
+}
+
+__global__ void __launch_bounds__(kThreads) k_bounds_b(const Plan *plans, const int32_t *offA,
+                                                       const int32_t *offB, const int32_t *offC, int count)
+{
+    const int b = blockIdx.x;
+    const int totA = uniform(offA[count]), totB = uniform(offB[count]);
+    if (b < totA) {
+        const int p = find_problem(offA, count, b);
+        const Plan P = uniform_plan(plans[p]);
+        bounds_A_body(P, b - uniform(offA[p]));
+    } else if (b < totA + totB) {
+        const int p = find_problem(offB, count, b - totA);
+        const Plan P = uniform_plan(plans[p]);
+        bounds_B_body(P, b - totA - uniform(offB[p]));
+    } else {
+        const int p = find_problem(offC, count, b - totA - totB);
+        const Plan P = uniform_plan(plans[p]);
+        bounds_C_body(P, b - totA - totB - uniform(offC[p]));
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_finalize_b(const Plan *plans)
+{
+    const Plan P = uniform_plan(plans[blockIdx.x]);
+    finalize_body(P);
+}
+
+__global__ void __launch_bounds__(kThreads) k_consistency_b(const Plan *plans, const int32_t *off, int count)
+{
+    const int p = find_problem(off, count, blockIdx.x);
+    const Plan P = uniform_plan(plans[p]);
+    consistency_body(P, consistency_per_tile(P.tm, P.tn), blockIdx.x - uniform(off[p]));
+}
+
+__global__ void __launch_bounds__(kThreads) k_dag_b(const Plan *plans, const uint64_t *tasks,
+                                                    const uint32_t *tprob, uint32_t ntasks,
+                                                    uint32_t *ticket_, double *scratch_base)
+{
+    __shared__ TaskLds L;
+    __shared__ uint32_t s_ticket;
+    __shared__ int s_ok;
+    uint32_t *ticket = uniptr(ticket_);
+    double *scratch = uniptr(scratch_base) + (size_t)blockIdx.x * kMaxTile * kMaxTile;
+    const uint32_t nt = uni32((int)ntasks);
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t t = uniform(s_ticket);
+        if (t >= nt) break;
+        const uint64_t task = tasks[t];
+        const int p = uni32((int)tprob[t]);
+        const Plan P = uniform_plan(plans[p]);
+        const uint32_t slabs = (uint32_t)P.slabs;
+        const int kind = uniform(task_kind(task)), T = uniform(task_T(task));
+        if (threadIdx.x == 0) {
+            const bool bad = *(volatile int32_t *)P.status >= kBadStructure;
+            bool ok = true;
+            if (!bad) {
+                const uint64_t t0 = wall_clock64();
+                if (kind == kTaskSolve) {
+                    ok = wait_count(P, &P.ver[T], (uint32_t)tile_updates(P, T) * slabs, t0);
+                } else {
+                    const int S = task_S(task), u = task_u(task);
+                    ok = wait_count(P, &P.ver[S], (uint32_t)(tile_updates(P, S) + 1) * slabs, t0) &&
+                         wait_count(P, &P.ver[T], (uint32_t)u * slabs, t0);
+                }
+                if (!ok) set_status(P.status, kWatchdog);
+            }
+            s_ok = (ok && !bad) ? 1 : 0;
+        }
+        __syncthreads();
+        if (uniform(s_ok)) {
+            if (kind == kTaskSolve) run_solve(P, T, scratch, L.sol);
+            else run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd, nullptr);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&P.ver[T], kind == kTaskSolve ? slabs : 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
     }
 }
 
@@ -383,8 +499,7 @@ hipError_t launch_finalize(const Plan &P, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, P);
     if (P.pt * P.qt == 0) return hipGetLastError();
-    const int per = (P.tm * P.tn + kThreads - 1) / kThreads;
-    const int gx = per < 8 ? per : 8;
+    const int gx = consistency_per_tile(P.tm, P.tn);
     hipLaunchKernelGGL(k_consistency, dim3(gx * P.pt * P.qt), dim3(kThreads), 0, s, P, gx);
     return hipGetLastError();
 }
@@ -395,6 +510,24 @@ hipError_t launch_debug_protect(int which, int count, const double *in, int32_t 
     if (g == 0) return hipSuccess;
     if (which == 0) hipLaunchKernelGGL(k_debug_pu, dim3(g), dim3(256), 0, s, count, in, out);
     else hipLaunchKernelGGL(k_debug_pd, dim3(g), dim3(256), 0, s, count, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchedLaunch &b, hipStream_t s)
+{
+    if (b.count <= 0) return hipSuccess;
+    if (b.blocks_structure > 0)
+        hipLaunchKernelGGL(k_structure_b, dim3(b.blocks_structure), dim3(256), 0, s, b.plans, b.off_structure, b.count);
+    if (b.blocks_bounds > 0)
+        hipLaunchKernelGGL(k_bounds_b, dim3(b.blocks_bounds), dim3(kThreads), 0, s, b.plans, b.off_A, b.off_B, b.off_C,
+                           b.count);
+    if (b.ntasks > 0)
+        hipLaunchKernelGGL(k_dag_b, dim3(b.workers), dim3(kThreads), 0, s, b.plans, b.tasks, b.tprob,
+                           (uint32_t)b.ntasks, b.ticket, b.scratch);
+    hipLaunchKernelGGL(k_finalize_b, dim3(b.count), dim3(kThreads), 0, s, b.plans);
+    if (b.blocks_consistency > 0)
+        hipLaunchKernelGGL(k_consistency_b, dim3(b.blocks_consistency), dim3(kThreads), 0, s, b.plans,
+                           b.off_consistency, b.count);
     return hipGetLastError();
 }
 
