@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrsyl.so")
 ARCH = os.environ.get("TRSYL_ARCH", "gfx950")
 
-HIP_SOURCES = ["solver.hip", "refine.hip", "extras.hip"]
+HIP_SOURCES = ["solver.hip", "extras.hip"]
 HOST_SOURCES = ["capi.cpp", "capi_extras.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 # packed FP32 VALU forms are disabled for all device code
@@ -35,15 +35,11 @@ def build(verbose: bool = True, defines: tuple = ()) -> str:
     objs = []
     for src in HIP_SOURCES:
         path = os.path.join(CSRC, src)
-        if not os.path.exists(path):
-            continue
         obj = os.path.join(bdir, src + ".o")
         _run(["hipcc", "-c", path, "-o", obj] + COMMON + DEVICE + extra)
         objs.append(obj)
     for src in HOST_SOURCES:
         path = os.path.join(CSRC, src)
-        if not os.path.exists(path):
-            continue
         obj = os.path.join(bdir, src + ".o")
         _run(["hipcc", "-c", path, "-o", obj] + COMMON)
         objs.append(obj)
