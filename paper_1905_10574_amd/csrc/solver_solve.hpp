@@ -22,6 +22,7 @@
 #include "device_common.hpp"
 #include "plan.hpp"
 #include "solver_update.hpp"
+#include "solver_leaf.hpp"
 
 namespace trsyl {
 
@@ -34,22 +35,13 @@ namespace trsyl {
 #define TRSYL_STAMP(ptr, idx) do { (void)(ptr); } while (0)
 #endif
 
-constexpr int kLd = 17;          // leading dimension of the 16x16 LDS buffers
 constexpr int kMaxParts = kMaxLeaves > kWaves ? kMaxLeaves : kWaves;
-
-struct LeafLds {                 // 17 x 17 each; row 16 and column 16 stay zero
-    double R[17 * kLd];
-    double Al[17 * kLd];
-    double Bl[17 * kLd];
-};
 
 struct SolveLds {
     LeafLds leaf[kWaves];
     double part[kMaxParts][16 * kLd];   // split-K partial sums of the leaf GEMMs
     int la[kMaxLeaves + 1], lb[kMaxLeaves + 1];
     int nla, nlb;
-    int nsteps[kWaves];
-    uint32_t msteps[kWaves];
     int fail;
     // fallback
     int as[kMaxTile + 1], bs[kMaxTile + 1];
@@ -85,387 +77,6 @@ __device__ inline void leaf_offsets_wave(const double *Ad, int64_t lda, int mr, 
     if (valid) (isB ? lb : la)[k + 1] = bb;
     if (lane == 0) { la[0] = 0; la[na] = mr; *nla = na; }
     if (lane == 32) { lb[0] = 0; lb[nb] = nc; *nlb = nb; }
-}
-
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// ---------------------------------------------------------------------------------------------
-// Unguarded small solves of the speculative path: Gaussian elimination with complete pivoting
-// (the method of Sec. 2.1) without ProtectUpdate / ProtectDivision; the caller's magnitude
-// checks certify that no guard would have fired.  Return false if a pivot is below smin.
-// ---------------------------------------------------------------------------------------------
-// 2 unknowns: K [x0 x1]^T = [v0 v1]^T, K = [[k00, k01], [k10, k11]].
-__device__ __forceinline__ bool solve2_cp(double k00, double k01, double k10, double k11,
-                                          double &v0, double &v1, double smin)
-{
-    const double a00 = fabs(k00), a01 = fabs(k01), a10 = fabs(k10), a11 = fabs(k11);
-    const bool rsw = fmax(a10, a11) > fmax(a00, a01);        // pivot in row 1
-    double p0 = rsw ? k10 : k00, p1 = rsw ? k11 : k01;       // pivot row
-    double q0 = rsw ? k00 : k10, q1 = rsw ? k01 : k11;       // other row
-    double w0 = rsw ? v1 : v0, w1 = rsw ? v0 : v1;
-    const bool csw = fabs(p1) > fabs(p0);                    // pivot in column 1
-    if (csw) {
-        double t = p0; p0 = p1; p1 = t;
-        t = q0; q0 = q1; q1 = t;
-    }
-    if (fabs(p0) < smin) return false;
-    const double l = q0 / p0;
-    const double u11 = fma(-l, p1, q1);
-    if (fabs(u11) < smin) return false;
-    w1 = fma(-l, w0, w1);
-    const double x1 = w1 / u11;
-    const double x0 = fma(-p1, x1, w0) / p0;
-    v0 = csw ? x1 : x0;
-    v1 = csw ? x0 : x1;
-    return true;
-}
-
-// The same elimination split into a factorisation, done once per block when the leaf is set up
-// (pivot choices, multiplier, reciprocals of the pivots), and its application to a right-hand
-// side: two FMAs and two multiplications on the step's critical path instead of three divisions.
-// A 1x1 block uses rp0 alone (its reciprocal divisor).
-struct Factor2 {
-    double l, p1, rp0, ru11;
-    int sw;                    // bit 0: rows swapped, bit 1: columns swapped
-};
-__device__ __forceinline__ bool factor2_cp(double k00, double k01, double k10, double k11, double smin,
-                                           Factor2 &f)
-{
-    const bool rsw = fmax(fabs(k10), fabs(k11)) > fmax(fabs(k00), fabs(k01));
-    double p0 = rsw ? k10 : k00, p1 = rsw ? k11 : k01;
-    double q0 = rsw ? k00 : k10, q1 = rsw ? k01 : k11;
-    const bool csw = fabs(p1) > fabs(p0);
-    if (csw) {
-        double t = p0; p0 = p1; p1 = t;
-        t = q0; q0 = q1; q1 = t;
-    }
-    f.sw = (rsw ? 1 : 0) | (csw ? 2 : 0);
-    f.p1 = p1;
-    if (fabs(p0) < smin) { f.l = 0.0; f.rp0 = 0.0; f.ru11 = 0.0; return false; }
-    f.l = q0 / p0;
-    const double u11 = fma(-f.l, p1, q1);
-    f.rp0 = 1.0 / p0;
-    if (fabs(u11) < smin) { f.ru11 = 0.0; return false; }
-    f.ru11 = 1.0 / u11;
-    return true;
-}
-__device__ __forceinline__ void apply2(const Factor2 &f, double &v0, double &v1)
-{
-    double w0 = (f.sw & 1) ? v1 : v0, w1 = (f.sw & 1) ? v0 : v1;
-    w1 = fma(-f.l, w0, w1);
-    const double x1 = w1 * f.ru11;
-    const double x0 = fma(-f.p1, x1, w0) * f.rp0;
-    v0 = (f.sw & 2) ? x1 : x0;
-    v1 = (f.sw & 2) ? x0 : x1;
-}
-
-// 4 unknowns (2x2 A-block with 2x2 B-block): K = I (x) A11 + B11^T (x) I on vec(Z).
-__device__ __forceinline__ bool solve4_cp(const double (&a)[4], const double (&b)[4], double (&z)[4], double smin)
-{
-    double K[4][4], v[4];
-    int perm[4] = {0, 1, 2, 3};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int p = e & 1, q = e >> 1;
-        v[e] = z[e];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int pp = u & 1, qq = u >> 1;
-            double x = 0.0;
-            if (qq == q) x += a[pp * 2 + p];     // A(p, pp)
-            if (pp == p) x += b[q * 2 + qq];     // B(qq, q)
-            K[e][u] = x;
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        int pi = t, pj = t;
-        double best = -1.0;
-#pragma unroll
-        for (int i = t; i < 4; ++i)
-#pragma unroll
-            for (int j = t; j < 4; ++j)
-                if (fabs(K[i][j]) > best) { best = fabs(K[i][j]); pi = i; pj = j; }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double x = K[t][j];
-            double y = x;
-#pragma unroll
-            for (int i = t + 1; i < 4; ++i) if (i == pi) { y = K[i][j]; K[i][j] = x; }
-            K[t][j] = y;
-        }
-        {
-            const double x = v[t];
-            double y = x;
-#pragma unroll
-            for (int i = t + 1; i < 4; ++i) if (i == pi) { y = v[i]; v[i] = x; }
-            v[t] = y;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double x = K[i][t];
-            double y = x;
-#pragma unroll
-            for (int j = t + 1; j < 4; ++j) if (j == pj) { y = K[i][j]; K[i][j] = x; }
-            K[i][t] = y;
-        }
-        {
-            const int x = perm[t];
-            int y = x;
-#pragma unroll
-            for (int j = t + 1; j < 4; ++j) if (j == pj) { y = perm[j]; perm[j] = x; }
-            perm[t] = y;
-        }
-        if (fabs(K[t][t]) < smin) return false;
-#pragma unroll
-        for (int i = t + 1; i < 4; ++i) {
-            const double l = K[i][t] / K[t][t];
-#pragma unroll
-            for (int j = t + 1; j < 4; ++j) K[i][j] = fma(-l, K[t][j], K[i][j]);
-            v[i] = fma(-l, v[t], v[i]);
-        }
-    }
-#pragma unroll
-    for (int i = 3; i >= 0; --i) {
-#pragma unroll
-        for (int j = i + 1; j < 4; ++j) v[i] = fma(-K[i][j], v[j], v[i]);
-        v[i] = v[i] / K[i][i];
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) if (perm[t] == x) z[x] = v[t];
-    return true;
-}
-
-// ---------------------------------------------------------------------------------------------
-// Leaf solve: A_l Y + Y B_l = R on a leaf of nr x nc <= 16 x 16 held in L.R, with A_l, B_l in
-// L.Al, L.Bl (17 x 17, ld 17; row 16 and column 16 of all three arrays hold zeros), by a group of
-// 16 / E lanes-rows: lane gl of the group (0 <= gl < 256 / E) owns column c = gl & 15 and rows
-// q, q + Q, ... (q = gl >> 4, Q = 16 / E), E entries.  Every wave of the workgroup runs the step
-// loop in lockstep (one barrier per step, a second one on steps that finalise a 2x2 block), so
-// groups may span waves; waves without a leaf (active == false) only take part in the barriers.
-//
-// Block anti-diagonals s = 0, 1, ...: the blocks on diagonal s are solved (a 1x1 block in its own
-// lane; a block with 2 or 4 unknowns by the lane that owns its top-left entry, from values
-// published to LDS), then every pending entry subtracts the contributions of the block just
-// solved in its block column (below it) and in its block row (left of it).  A lane's rows lie in
-// distinct block rows (Q >= 4), so it finalises at most one entry per step.  The block structure
-// is kept as bit masks; each lane walks its column source upwards and each entry's row source
-// rightwards one block per step, a missing source pointing at the zero row / column 16, so every
-// contribution is four unconditional FMAs.  An entry stops changing once final.  The certificate
-// bound is a running maximum: the first non-finite value a step can produce is an infinity (all
-// operands are finite, divisors at least smin), which the maximum keeps.  Returns 1 if the
-// certificate held for this lane.
-// ---------------------------------------------------------------------------------------------
-struct LeafMasks {
-    uint32_t rmask, cmask, m2, n2;   // first rows / columns of blocks, of 2x2 blocks
-    int na, nb;
-};
-// Steps s that finalise a block with 2 or 4 unknowns: block (Ib, Jb) is final at step
-// (na - 1 - Ib) + Jb, so a 2x2 block row Ib marks steps na - 1 - Ib + [0, nb) and a 2x2 block
-// column Jb marks steps Jb + [0, na).
-__device__ __forceinline__ uint32_t multi_steps(const LeafMasks &M)
-{
-    uint32_t ms = 0u;
-    for (uint32_t x = M.m2; x; x &= x - 1u) {
-        const int r = __ffs((int)x) - 1;
-        const int Ib = __popc(M.rmask & ((1u << r) - 1u));
-        ms |= ((1u << M.nb) - 1u) << (M.na - 1 - Ib);
-    }
-    for (uint32_t x = M.n2; x; x &= x - 1u) {
-        const int c = __ffs((int)x) - 1;
-        const int Jb = __popc(M.cmask & ((1u << c) - 1u));
-        ms |= ((1u << M.na) - 1u) << Jb;
-    }
-    return ms;
-}
-__device__ __forceinline__ LeafMasks leaf_masks(const LeafLds &L, int nr, int nc)
-{
-    const int lane = threadIdx.x & 63;
-    const bool rstart = (lane < nr) && (lane == 0 || L.Al[(lane - 1) * kLd + lane] == 0.0);
-    const bool cstart = (lane < nc) && (lane == 0 || L.Bl[(lane - 1) * kLd + lane] == 0.0);
-    LeafMasks M;
-    M.rmask = (uint32_t)__ballot(rstart);
-    M.cmask = (uint32_t)__ballot(cstart);
-    M.m2 = M.rmask & ~(M.rmask >> 1) & ((1u << (nr - 1)) - 1u);
-    M.n2 = M.cmask & ~(M.cmask >> 1) & ((1u << (nc - 1)) - 1u);
-    M.na = __popc(M.rmask);
-    M.nb = __popc(M.cmask);
-    return M;
-}
-
-// E entries per lane; E == 4 means one wave per leaf, which synchronises at wave level and runs
-// its own step count.  For E < 4 all waves step together: `steps` and `msteps` (the OR of the
-// groups' multi_steps masks) are the same in every wave.
-template <int E>
-__device__ int leaf_solve_group(LeafLds &L, int nr, int nc, double smin, double Tc, bool active,
-                                int gl, int steps, uint32_t msteps)
-{
-    constexpr bool kWG = E < 4;
-    constexpr int Q = 16 / E;
-    const int c = gl & 15, q = gl >> 4;
-    LeafMasks M{0u, 0u, 0u, 0u, 1, 1};
-    if (active) M = leaf_masks(L, nr, nc);
-    if (!kWG) {
-        steps = M.na + M.nb - 1;
-        msteps = multi_steps(M);
-    }
-    const uint32_t rmask = M.rmask, cmask = M.cmask, m2 = M.m2, n2 = M.n2;
-    const int na = M.na;
-    const bool cvalid = active && c < nc;
-    const uint32_t cle = cmask & ((2u << c) - 1u);
-    const int Jc = __popc(cle) - 1;                  // my block column
-    const int cb0 = cle ? 31 - __clz(cle) : 0;       // its first column
-    const int csz = 1 + ((n2 >> cb0) & 1);
-    const double bcc = active ? L.Bl[c * kLd + c] : 1.0;
-
-    int ok = 1;
-    double vmax = 0.0;
-    double acc[E];
-    Factor2 fac[E];                                  // 1x1: fac.rp0 = 1 / (a_rr + b_cc)
-    int fin[E], rowst[E], cs[E], rsz[E];
-    bool own[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int r = q + Q * i;
-        const bool valid = cvalid && r < nr;
-        const uint32_t rle = rmask & ((2u << r) - 1u);
-        const int Ir = __popc(rle) - 1;              // my block row
-        const int rb0 = rle ? 31 - __clz(rle) : 0;
-        rsz[i] = 1 + ((m2 >> rb0) & 1);
-        rowst[i] = na - 1 - Ir;                      // first step with a row source
-        fin[i] = valid ? rowst[i] + Jc : -1;         // step at which the entry is final
-        cs[i] = 0;
-        own[i] = valid && r == rb0 && c == cb0;
-        acc[i] = active ? L.R[c * kLd + r] : 0.0;
-        fac[i] = Factor2{0.0, 0.0, 1.0, 0.0, 0};
-        if (valid && rsz[i] == 1 && csz == 1) {
-            const double dd = L.Al[r * kLd + r] + bcc;
-            if (fabs(dd) < smin) ok = 0;
-            fac[i].rp0 = 1.0 / dd;
-        } else if (own[i] && rsz[i] * csz == 2) {
-            bool good;
-            if (rsz[i] == 2)   // (A11 + b I) z = r over the two rows
-                good = factor2_cp(L.Al[r * kLd + r] + bcc, L.Al[(r + 1) * kLd + r], L.Al[r * kLd + r + 1],
-                                  L.Al[(r + 1) * kLd + r + 1] + bcc, smin, fac[i]);
-            else               // z (a I + B11) = r over the two columns
-                good = factor2_cp(L.Al[r * kLd + r] + bcc, L.Bl[c * kLd + c + 1], L.Bl[(c + 1) * kLd + c],
-                                  L.Al[r * kLd + r] + L.Bl[(c + 1) * kLd + c + 1], smin, fac[i]);
-            if (!good) ok = 0;
-        }
-    }
-    int rsc = rmask ? 31 - __clz(rmask) : -1;       // first row of the column source block
-    for (int s = 0; s < steps; ++s) {
-        bool multi = false, ownk = false;
-        int rk = 0, rszk = 1;
-        Factor2 fk{0.0, 0.0, 1.0, 0.0, 0};
-        int ia0 = 16, ia1 = 16;
-        bool colv = false;
-        double a0[E], a1[E], b0[E], b1[E];
-        int ib0[E], ib1[E];
-        if (active) {
-            // this step's sources and their coefficients (independent of the step's values)
-            colv = s >= Jc && rsc >= 0;
-            ia0 = colv ? rsc : 16;
-            ia1 = (colv && ((m2 >> rsc) & 1)) ? rsc + 1 : 16;
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int r = q + Q * i;
-                a0[i] = L.Al[ia0 * kLd + r];
-                a1[i] = L.Al[ia1 * kLd + r];
-                const bool rowv = s >= rowst[i] && cs[i] < cb0;
-                ib0[i] = rowv ? cs[i] : 16;
-                ib1[i] = (rowv && ((n2 >> cs[i]) & 1)) ? cs[i] + 1 : 16;
-                b0[i] = L.Bl[c * kLd + ib0[i]];
-                b1[i] = L.Bl[c * kLd + ib1[i]];
-            }
-            // the entry this lane finalises at step s, if any
-            bool act = false;
-            double ak = 0.0;
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                if (fin[i] == s) {
-                    act = true;
-                    ak = acc[i];
-                    fk = fac[i];
-                    rk = q + Q * i;
-                    rszk = rsz[i];
-                    ownk = own[i];
-                }
-            }
-            if (act) {
-                double y = ak;
-                if (rszk == 1 && csz == 1) {
-                    y = ak * fk.rp0;
-                    vmax = fmax(vmax, fabs(y));
-                } else {
-                    multi = true;
-                }
-                L.R[c * kLd + rk] = y;
-            }
-        }
-        if (kWG) __syncthreads();
-        else wave_sync_lds();
-        if ((msteps >> s) & 1u) {
-            if (multi && ownk) {
-                const int ra = rk;
-                double a[4], b[4], z[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int p = t & 1, pp = t >> 1;   // column-major 2x2 position (p, pp)
-                    a[t] = (p < rszk && pp < rszk) ? L.Al[(ra + pp) * kLd + ra + p] : 0.0;
-                    b[t] = (p < csz && pp < csz) ? L.Bl[(c + pp) * kLd + c + p] : 0.0;
-                    z[t] = (p < rszk && pp < csz) ? L.R[(c + pp) * kLd + ra + p] : 0.0;
-                }
-                if (rszk == 2 && csz == 2) {
-                    if (!solve4_cp(a, b, z, smin)) ok = 0;
-                } else if (rszk == 2) {   // factors of (A11 + b I), unknowns down the column
-                    apply2(fk, z[0], z[1]);
-                } else {                  // factors of (a I + B11), unknowns along the row
-                    apply2(fk, z[0], z[2]);
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int p = t & 1, pp = t >> 1;
-                    if (p < rszk && pp < csz) {
-                        vmax = fmax(vmax, fabs(z[t]));
-                        L.R[(c + pp) * kLd + ra + p] = z[t];
-                    }
-                }
-            }
-            if (kWG) __syncthreads();
-            else wave_sync_lds();
-        }
-        if (active) {
-            // contributions of the blocks solved at step s
-            const double y0 = L.R[c * kLd + ia0], y1 = L.R[c * kLd + ia1];
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int r = q + Q * i;
-                double v = acc[i];
-                v = fma(-a0[i], y0, v);
-                v = fma(-a1[i], y1, v);
-                v = fma(-L.R[ib0[i] * kLd + r], b0[i], v);
-                v = fma(-L.R[ib1[i] * kLd + r], b1[i], v);
-                if (s < fin[i]) {
-                    acc[i] = v;
-                    vmax = fmax(vmax, fabs(v));
-                }
-            }
-            // advance the sources by one block
-            if (colv) rsc -= (rsc >= 2 && ((m2 >> (rsc - 2)) & 1)) ? 2 : 1;
-#pragma unroll
-            for (int i = 0; i < E; ++i)
-                if (s >= rowst[i] && cs[i] < cb0) cs[i] += 1 + ((n2 >> cs[i]) & 1);
-        }
-    }
-    if (!(vmax <= Tc)) ok = 0;
-    return ok;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -609,71 +220,36 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
         }
         __syncthreads();
         TRSYL_STAMP(stamp, 4 + 2 * d);
-        // phase B: the front's leaves in rounds.  A round takes up to 8 / G leaves with G waves
-        // each (G = 4, 2, 1 for at most 2, 4, 8 remaining leaves); wave k fills slot k with leaf
-        // li0 + k (its right-hand side minus the partial sums in order), the groups solve in
-        // lockstep, and wave k stores slot k to S.
-        for (int li0 = 0; li0 < nleaf;) {
-            const int rem = nleaf - li0;
-            const int G = rem <= 2 ? 4 : 1;
-            const int nl = rem < kWaves / G ? rem : kWaves / G;
-            if (w < nl) {
-                const int li = li0 + w, J = jlo + li, I = nla - 1 - (d - J);
-                if (li0 > 0) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
-                const int nr = L.la[I + 1] - L.la[I], ncl = L.lb[J + 1] - L.lb[J];
+        // phase B: wave k takes leaves k, k + 8, ...: fills its buffer with the leaf's right-hand
+        // side minus the partial sums (added in order), solves the leaf and stores it to S.
+        for (int li = w; li < nleaf; li += kWaves) {
+            const int J = jlo + li, I = nla - 1 - (d - J);
+            if (li >= kWaves) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
+            const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
+            const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
-                    double v = 0.0;
-                    if (mm < nr && nn < ncl) {
-                        double g = 0.0;
-                        for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
-                        v = rhs[i] - g;
-                        if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
-                    }
-                    LL.R[nn * kLd + mm] = v;
+            for (int i = 0; i < 4; ++i) {
+                const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                double v = 0.0;
+                if (mm < nr && nn < ncl) {
+                    double g = 0.0;
+                    for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
+                    v = rhs[i] - g;
+                    if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
                 }
-                wave_sync_lds();
-                const LeafMasks M = leaf_masks(LL, nr, ncl);
-                if (lane == 0) {
-                    L.nsteps[w] = M.na + M.nb - 1;
-                    L.msteps[w] = multi_steps(M);
-                }
+                LL.R[nn * kLd + mm] = v;
             }
-            __syncthreads();
-            int steps = 0;
-            uint32_t msteps = 0u;
-            for (int k = 0; k < nl; ++k) {
-                steps = L.nsteps[k] > steps ? L.nsteps[k] : steps;
-                msteps |= L.msteps[k];
-            }
-            steps = uniform(steps);
-            msteps = uniform(msteps);
-            if (li0 == 0) TRSYL_STAMP(stamp, 40 + 2 * d);
-            const int k = w / G;
-            const bool active = k < nl;
-            const int gl = (w % G) * 64 + lane;
-            const int ks = active ? k : 0;
-            const int Jk = jlo + li0 + ks, Ik = nla - 1 - (d - Jk);
-            const int nrk = L.la[Ik + 1] - L.la[Ik], nck = L.lb[Jk + 1] - L.lb[Jk];
-            int okk;
-            if (G == 4) okk = leaf_solve_group<1>(L.leaf[ks], nrk, nck, smin, Tc, active, gl, steps, msteps);
-            else if (G == 2) okk = leaf_solve_group<2>(L.leaf[ks], nrk, nck, smin, Tc, active, gl, steps, msteps);
-            else okk = leaf_solve_group<4>(L.leaf[ks], nrk, nck, smin, Tc, active, gl, steps, msteps);
-            if (!okk) ok = 0;
-            __syncthreads();
-            if (li0 == 0) TRSYL_STAMP(stamp, 41 + 2 * d);
-            if (w < nl) {
-                const int li = li0 + w, J = jlo + li, I = nla - 1 - (d - J);
-                const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
-                const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+            wave_sync_lds();
+            if (li == 0) TRSYL_STAMP(stamp, 40 + 2 * d);
+            const LeafMasks M = leaf_masks(LL, nr, ncl);
+            if (!leaf_setup(LL, M, smin)) ok = 0;
+            if (!leaf_solve(LL, nr, ncl, smin, Tc, M)) ok = 0;
+            if (li == 0) TRSYL_STAMP(stamp, 41 + 2 * d);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
-                    if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
-                }
+            for (int i = 0; i < 4; ++i) {
+                const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
             }
-            li0 += nl;
         }
         if (!ok) L.fail = 1;
         __threadfence_block();
