@@ -37,12 +37,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dag_8192_separated_fp64_traffic
 
 
 def kernel_sources_digest() -> str:
-    """SHA-256 over the device sources (csrc/*.hip, *.hpp), names and contents in name order."""
+    """SHA-256 over the library sources (csrc/*.hip, *.hpp, *.cpp: the kernels and the task order
+    they run), names and contents in name order."""
     import hashlib
     d = os.path.join(ROOT, "paper_1905_10574_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
+        if f.endswith((".hip", ".hpp", ".cpp")):
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
