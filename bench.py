@@ -103,6 +103,69 @@ def cpu_baseline(size: int, threads: int):
                       f"{dt:.1f} s"}
 
 
+def paper_sweeps(args):
+    """The workloads of the paper's experiments (Sec. 4): C and the strict upper parts of A, B are
+    ones, the diagonal blocks mu T / nu T with T = [1] or [[1, 1], [-1, 1]] (a 2x2 block starts
+    with probability 0.1 while walking down the diagonal; the paper leaves the pattern open).
+    Per point: one warm-up solve, then the median of --paper-reps timed solves (host wall clock
+    around each stream-synchronised solve), the scaling exponent e, the scaling-event counters
+    and eq. (9)."""
+    import statistics
+    import torch
+    import paper_1905_10574_amd as T
+    import trsyl_workloads as W
+
+    dev = torch.device("cuda:0")
+    points = [("no scaling (mu = m, nu = n)", int(s), None, None) for s in args.paper_sizes.split(",") if s]
+    points += [("cost of robustness (nu = 1e-2)", args.paper_robust_size, mu, 1e-2)
+               for mu in (1e2, 10.0, 1.0, 1e-3, 1e-7)]
+    L = T.lib()
+    for (kind, m, mu, nu) in points:
+        mu_v = float(m) if mu is None else mu
+        nu_v = float(m) if nu is None else nu
+        print(f"[paper] m=n={m} mu={mu_v:g} nu={nu_v:g}: generating", file=sys.stderr, flush=True)
+        A_np, B_np, C_np = W.paper_problem(args.seed, m, m, mu_v, nu_v, p2x2=0.1)
+        Ac, Bc, C0 = T.colmajor(A_np, dev), T.colmajor(B_np, dev), T.colmajor(C_np, dev)
+        del A_np, B_np
+        opts = T.make_opts()
+        ws_bytes = T.workspace_size(m, m, opts)
+        ws_keep, ws_ptr = T._aligned_workspace(ws_bytes, dev)
+        cnt = torch.zeros(4, dtype=torch.int32, device=dev)
+        opts.counters = cnt.data_ptr()
+        e_t = torch.zeros(1, dtype=torch.int64, device=dev)
+        sc_t = torch.zeros(1, dtype=torch.float64, device=dev)
+        info_t = torch.zeros(1, dtype=torch.int32, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        times = []
+        Yc = None
+        for rep in range(1 + args.paper_reps):
+            Yc = C0.clone()
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            rc = L.trsyl_robust(m, m, Ac.data_ptr(), m, Bc.data_ptr(), m, Yc.data_ptr(), m, e_t.data_ptr(),
+                                sc_t.data_ptr(), info_t.data_ptr(), ctypes.byref(opts), ws_ptr, ws_bytes, stream)
+            if rc != 0:
+                raise RuntimeError(f"trsyl_robust returned {rc}")
+            torch.cuda.synchronize(dev)
+            dt = time.perf_counter() - t0
+            print(f"[paper]   solve {rep} ({'warm-up' if rep == 0 else 'timed'}): {1e3 * dt:.2f} ms",
+                  file=sys.stderr, flush=True)
+            if rep > 0:
+                times.append(dt)
+        e = int(e_t.item())
+        resid = residual_lib(T, Ac, Bc, Yc, e_t, C0, m, m)
+        c = cnt.cpu().tolist()
+        t = statistics.median(times)
+        print(json.dumps({"workload": "paper test matrices", "points": kind, "m": m, "n": m, "mu": mu_v,
+                          "nu": nu_v, "p2x2": 0.1, "ms_median": round(1e3 * t, 3),
+                          "gflops": round(W.flop_count(m, m) / t / 1e9, 2), "scale_log2": e,
+                          "info": int(info_t.item()), "fallback_tile_solves": c[0],
+                          "scaled_tile_updates": c[1], "residual_eq9": resid,
+                          "tiles": (m + 127) // 128, "reps": args.paper_reps}), flush=True)
+        del Ac, Bc, C0, Yc, ws_keep
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +181,13 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the FP32+refine measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the eq. (9) residual check")
+    ap.add_argument("--paper", action="store_true",
+                    help="run the paper's experiment workloads instead (Sec. 4 test matrices): mu = m, "
+                         "nu = n at the --paper-sizes, then the cost-of-robustness sweep nu = 1e-2, "
+                         "mu in {1e2, 10, 1, 1e-3, 1e-7} at --paper-robust-size; one JSON line each")
+    ap.add_argument("--paper-sizes", default="1000,2000,10000,20000")
+    ap.add_argument("--paper-robust-size", type=int, default=10000)
+    ap.add_argument("--paper-reps", type=int, default=3, help="timed solves per point (median)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run three plain device-to-device copies of BYTES bytes (the reference "
                          "kernel that scales the HBM byte counters) and exit")
@@ -133,6 +203,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 8 * n, "copies": 3}))
         return
+
+    if args.paper:
+        return paper_sweeps(args)
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "

@@ -32,7 +32,7 @@ class Opts(ctypes.Structure):
                 ("slabs", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("workers", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("profile_events", ctypes.c_void_p),
-                ("trace", ctypes.c_void_p)]
+                ("trace", ctypes.c_void_p), ("counters", ctypes.c_void_p)]
 
 
 _lib = None
@@ -152,11 +152,22 @@ def solve_async(A, B, C, opts: Opts | None = None, *, workspace=None):
     return Yc, e, sc, info
 
 
-def solve(A, B, C, **kw):
-    """Robust solve; returns (Y (m x n, column-major view), e (alpha = 2^-e), info)."""
-    Yc, e, sc, info = solve_async(A, B, C, make_opts(**kw))
+def solve(A, B, C, *, counters=False, **kw):
+    """Robust solve; returns (Y (m x n, column-major view), e (alpha = 2^-e), info), and with
+    counters=True also the scaling-event counts {"fallback_solves", "scaled_updates"}."""
+    opts = make_opts(**kw)
+    cnt = None
+    if counters:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        cnt = torch.zeros(4, dtype=torch.int32, device=dev)
+        opts.counters = cnt.data_ptr()
+    Yc, e, sc, info = solve_async(A, B, C, opts)
     torch.cuda.synchronize(Yc.device)
-    return Yc.t(), int(e.item()), int(info.item())
+    out = (Yc.t(), int(e.item()), int(info.item()))
+    if counters:
+        c = cnt.cpu().tolist()
+        out = out + ({"fallback_solves": c[0], "scaled_updates": c[1]},)
+    return out
 
 
 def debug_protect_update(args) -> list[int]:

@@ -28,6 +28,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Resolved {
     int tm, tn, slabs, precision, scheduler, max_sweeps, workers, flags;
     double refine_tol;
+    uint32_t *counters;
 };
 
 int device_cus()
@@ -66,6 +67,7 @@ int resolve(const trsyl_opts *o, Resolved *r, int argpos)
     r->refine_tol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
     r->workers = o->workers > 0 ? o->workers : 0;
     r->flags = o->flags;
+    r->counters = o->counters;
     return 0;
 }
 
@@ -286,6 +288,7 @@ int solve_core(int64_t m, int64_t n, const double *A, int64_t lda, const double 
         if (launch_fill_zero(ws, kAlign, stream) != hipSuccess) return -100;
         // finalize with no tiles writes e = 0, alpha = 1 and the (zero) status
         P.status = (int32_t *)(ws + 8);
+        if (r.counters && launch_fill_zero(r.counters, 16, stream) != hipSuccess) return -100;
         return launch_finalize(P, stream) == hipSuccess ? 0 : -100;
     }
     if (launch_fill_zero(ws + L.zero_begin, L.zero_end - L.zero_begin, stream) != hipSuccess) return -100;
@@ -304,6 +307,9 @@ int solve_core(int64_t m, int64_t n, const double *A, int64_t lda, const double 
     }
     if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
     if (launch_finalize(P, stream) != hipSuccess) return -100;
+    if (r.counters && hipMemcpyAsync(r.counters, P.stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                     stream) != hipSuccess)
+        return -100;
     return 0;
 }
 
@@ -326,6 +332,8 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
 {
     Resolved rc = r;
     rc.precision = TRSYL_FP64;
+    Resolved rsweep = rc;          // the correction solves leave the caller's counters alone
+    rsweep.counters = nullptr;
     const size_t core = make_layout(m, n, rc).total;
     const size_t mn = 8 * (size_t)m * n;
     double *C0 = (double *)(ws + core);
@@ -368,7 +376,7 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
         g.Cin = D; g.ldcin = mi;
         g.ce1 = 0; g.ce2 = 0;
         if (launch_gemm(g, stream) != hipSuccess) return -100;
-        rcode = solve_core(m, n, A, lda, B, ldb, D, m, eD, nullptr, infoD, rc, kFlagF32Updates, ws, nullptr,
+        rcode = solve_core(m, n, A, lda, B, ldb, D, m, eD, nullptr, infoD, rsweep, kFlagF32Updates, ws, nullptr,
                            nullptr, stream);
         if (rcode) return rcode;
         if (launch_absmax_exp(D, m, mi, ni, part, sD, stream) != hipSuccess) return -100;

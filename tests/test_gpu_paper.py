@@ -1,0 +1,98 @@
+"""GPU tests on the test matrices of the paper's experiments (Sec. 4): C and the strict upper
+parts of A and B are ones, the diagonal blocks are mu T and nu T with T = [1] or
+[[1, 1], [-1, 1]].  mu and nu control the growth of the substitution:
+
+  * mu = m, nu = n: no scaling is needed (e = 0, no scaling event in any tile solve or update),
+    and the solution matches the oracle to 1e-10;
+  * nu = 1e-2 with mu in {1e2, 10}: no scaling either; mu in {1e-3, 1e-7}: frequent scaling
+    (e > 1000, scaling events counted), the result stays finite and below Omega, and the
+    normalised solution matches the oracle's to the bound its own spread between two tile
+    sizes allows;
+  * every case satisfies eq. (9) <= 1e-13.
+The scaling-event counts come through the counters option of the C ABI.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import trsyl_workloads as W
+
+pytestmark = pytest.mark.gpu
+OMEGA = 2.0 ** 1022
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_10574_amd as T
+    T.lib()
+    return T
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _normalised(Y):
+    mx = np.abs(Y).max()
+    if mx == 0:
+        return Y.copy()
+    return np.ldexp(Y, -math.frexp(mx)[1])
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_paper_no_scaling(T, orc):
+    m = n = 300
+    A, B, C = W.paper_problem(0, m, n, float(m), float(n), p2x2=0.1)
+    print(f"  gpu solve paper mu=m nu=n m=n={m}", flush=True)
+    Y, e, info, cnt = T.solve(A, B, C, tile=64, counters=True)
+    Y = Y.cpu().numpy()
+    assert info == 0 and e == 0
+    assert cnt == {"fallback_solves": 0, "scaled_updates": 0}
+    Yo, eo, _ = orc.drsylv(A, B, C, 64)
+    assert eo == 0
+    assert _rel(Y, Yo) <= 1e-10
+    assert T.residual(A, B, Y, e, C) <= 1e-13
+
+
+@pytest.mark.parametrize("mu", [1e2, 10.0, 1e-3, 1e-7])
+def test_paper_cost_of_robustness(T, orc, mu):
+    m = n = 300
+    A, B, C = W.paper_problem(0, m, n, mu, 1e-2, p2x2=0.1)
+    print(f"  gpu solve paper mu={mu} nu=1e-2 m=n={m}", flush=True)
+    Y, e, info, cnt = T.solve(A, B, C, tile=64, counters=True)
+    Y = Y.cpu().numpy()
+    assert info == 0
+    assert np.all(np.isfinite(Y)) and np.abs(Y).max() <= OMEGA
+    assert T.residual(A, B, Y, e, C) <= 1e-13
+    Yo, eo, _ = orc.drsylv(A, B, C, 64)
+    if mu >= 10.0:
+        assert e == 0 and eo == 0
+        assert cnt == {"fallback_solves": 0, "scaled_updates": 0}
+        assert _rel(Y, Yo) <= 1e-10
+    else:
+        assert e > 1000 and eo > 1000
+        assert cnt["fallback_solves"] + cnt["scaled_updates"] > 0
+        Yo2, _, _ = orc.drsylv(A, B, C, 32)
+        spread = _rel(_normalised(Yo2), _normalised(Yo))
+        err = _rel(_normalised(Y), _normalised(Yo))
+        print(f"    e_gpu={e} e_orc={eo} counters={cnt} err={err:.2e} oracle spread={spread:.2e}")
+        assert err <= max(1e-8, 100 * spread)
+
+
+def test_counters_empty(T):
+    A = np.eye(5)
+    B = np.zeros((0, 0))
+    C = np.zeros((5, 0))
+    Y, e, info, cnt = T.solve(A, B, C, counters=True)
+    assert e == 0 and info == 0
+    assert cnt == {"fallback_solves": 0, "scaled_updates": 0}
