@@ -159,8 +159,8 @@ def paper_sweeps(args):
         print(json.dumps({"workload": "paper test matrices", "points": kind, "m": m, "n": m, "mu": mu_v,
                           "nu": nu_v, "p2x2": 0.1, "ms_median": round(1e3 * t, 3),
                           "gflops": round(W.flop_count(m, m) / t / 1e9, 2), "scale_log2": e,
-                          "info": int(info_t.item()), "fallback_tile_solves": c[0],
-                          "scaled_tile_updates": c[1], "residual_eq9": resid,
+                          "info": int(info_t.item()), "leaf_tiled_tile_solves": c[2],
+                          "fallback_tile_solves": c[0], "scaled_tile_updates": c[1], "residual_eq9": resid,
                           "tiles": (m + 127) // 128, "reps": args.paper_reps}), flush=True)
         del Ac, Bc, C0, Yc, ws_keep
         torch.cuda.empty_cache()

@@ -75,10 +75,12 @@ typedef struct trsyl_opts {
                              of the persistent scheduler, [4t] = task word, [4t+1] = start and
                              [4t+2] = end (100 MHz wall clock), [4t+3] = workgroup */
     uint32_t *counters;   /* optional device buffer of 4 uint32, written on `stream` after the
-                             solve: [0] tile solves whose speculative certificate failed, so
-                             that Algorithm 2 ran with its scaling (Sec. 3), [1] tile updates
-                             whose scale decision rescaled the target or the solved tile
-                             (scaling events of RobustUpdate, Algorithm 3), [2..3] zero.
+                             solve: [0] tile solves that ran Algorithm 2 element by element
+                             (both faster paths failed), [1] tile updates whose scale decision
+                             rescaled the target or the solved tile (scaling events of
+                             RobustUpdate, Algorithm 3), [2] tile solves whose unscaled
+                             certificate failed, so that the leaf-tiled robust solve ran,
+                             [3] zero.
                              trsyl_robust and trsyl_robust_adjoint fill it (for
                              TRSYL_FP32_REFINE: the counts of the first, FP32-update solve);
                              trsyl_robust_batched ignores it */

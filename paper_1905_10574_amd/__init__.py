@@ -154,7 +154,8 @@ def solve_async(A, B, C, opts: Opts | None = None, *, workspace=None):
 
 def solve(A, B, C, *, counters=False, **kw):
     """Robust solve; returns (Y (m x n, column-major view), e (alpha = 2^-e), info), and with
-    counters=True also the scaling-event counts {"fallback_solves", "scaled_updates"}."""
+    counters=True also the scaling-event counts {"fallback_solves" (element-level Algorithm 2),
+    "scaled_updates", "scaled_solves" (leaf-tiled robust tile solves)}."""
     opts = make_opts(**kw)
     cnt = None
     if counters:
@@ -166,7 +167,7 @@ def solve(A, B, C, *, counters=False, **kw):
     out = (Yc.t(), int(e.item()), int(info.item()))
     if counters:
         c = cnt.cpu().tolist()
-        out = out + ({"fallback_solves": c[0], "scaled_updates": c[1]},)
+        out = out + ({"fallback_solves": c[0], "scaled_updates": c[1], "scaled_solves": c[2]},)
     return out
 
 

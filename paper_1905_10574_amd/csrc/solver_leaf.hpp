@@ -337,9 +337,11 @@ __device__ __forceinline__ int leaf_setup(LeafLds &L, const LeafMasks &M, double
 // ---------------------------------------------------------------------------------------------
 // The step loop.  Returns 0 in a lane where a pivot fell below smin or a value it produced
 // exceeded Tc (the first non-finite value is an infinity, which the running maximum keeps).
+// With vmax_out, the lane's largest magnitude is stored there instead and only the pivots
+// decide the return value.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc,
-                                          const LeafMasks &M)
+                                          const LeafMasks &M, double *vmax_out = nullptr)
 {
     constexpr int E = 4;
     const int lane = threadIdx.x & 63;
@@ -522,7 +524,8 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
         if (s + 1 < steps) step(s + 1, TB, TA, CB, CA);
     }
     wave_sync_lds();
-    if (!(vmax <= Tc)) ok = 0;
+    if (vmax_out) *vmax_out = vmax;
+    else if (!(vmax <= Tc)) ok = 0;
     return ok;
 }
 

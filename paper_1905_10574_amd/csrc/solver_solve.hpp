@@ -43,12 +43,23 @@ struct SolveLds {
     int la[kMaxLeaves + 1], lb[kMaxLeaves + 1];
     int nla, nlb;
     int fail;
-    // fallback
-    int as[kMaxTile + 1], bs[kMaxTile + 1];
-    double anorm_above[kMaxTile];
-    double bnorm_right[kMaxTile];
-    double z[4];
-    int zinfo[4];
+    union {
+        struct {   // Algorithm 2 on the whole tile
+            int as[kMaxTile + 1], bs[kMaxTile + 1];
+            double anorm_above[kMaxTile];
+            double bnorm_right[kMaxTile];
+            double z[4];
+            int zinfo[4];
+        };
+        struct {   // the leaf-tiled robust solve: per leaf (I, J) at [I * kMaxLeaves + J]
+            int eL[kMaxLeaves * kMaxLeaves];        // scale exponent: the leaf holds 2^-e X_IJ
+            double nL[kMaxLeaves * kMaxLeaves];     // ||Y_IJ||_inf of the stored leaf
+            double nC[kMaxLeaves * kMaxLeaves];     // ||C_IJ||_inf of the tile's right-hand side
+            double aN[kMaxLeaves * kMaxLeaves];     // ||A_IK||_inf, leaf blocks of A_kk (I <= K)
+            double bN[kMaxLeaves * kMaxLeaves];     // ||B_LJ||_inf, leaf blocks of B_ll (L <= J)
+            uint8_t rowleaf[kMaxTile + 1], colleaf[kMaxTile + 1];
+        };
+    };
     double red[kWaves];
 };
 
@@ -260,6 +271,274 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
     asm volatile("" ::"v"(warm));
     __syncthreads();
     return uniform(L.fail) ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Leaf-tiled robust tile solve: Algorithm 4 one level down, with the tile's leaves as tiles.
+// Leaf (I, J) carries a scale exponent e_IJ (the stored leaf is 2^-e_IJ times the solution block
+// X_IJ).  Its right-hand side C_IJ - sum_K A_IK X_KJ - sum_L X_IL B_LJ is formed at
+// e_IJ = max(0, e of the sources) + s, with s >= 0 the smallest shift such that
+//   2^-s (||C_IJ|| 2^-emax + sum_K ||A_IK|| ||Y_KJ|| 2^(e_KJ-emax) + sum_L ||Y_IL|| ||B_LJ|| 2^(e_IL-emax))
+// is at most Tc (the bound of Algorithm 3's ProtectUpdate summed over all the update's terms,
+// which also bounds every partial sum); each source enters multiplied by the exact power of two
+// 2^(e_src - e_IJ) as it is loaded.  The leaf is solved by the unscaled leaf solve; if a value
+// exceeds Tc, the right-hand side is divided by a further power of two chosen from the largest
+// magnitude seen (a linear rescaling) and the leaf is solved again.  At the end every leaf is
+// brought to the largest exponent (the consistency scaling of Algorithm 4) and that exponent is
+// returned: the scratch tile then holds 2^-e X with beta = 2^-e.  Returns -1 when a pivot falls
+// below smin or a leaf cannot be brought into range; the caller then runs Algorithm 2.
+// ---------------------------------------------------------------------------------------------
+constexpr int kML = kMaxLeaves;
+
+__device__ __forceinline__ void lds_max_nonneg(double *p, double v)
+{
+    atomicMax((unsigned long long *)p, (unsigned long long)__double_as_longlong(v));
+}
+
+// Row-sum norms of the leaf blocks of an mr x nc matrix (thread r sums row r; columns c >= c_lo(r)),
+// max-reduced per (row leaf, column leaf) into out[I * kML + J].  X(r, c) = get(r, c).
+template <class Get>
+__device__ __forceinline__ void leaf_block_norms(int rows, int cols, bool upper, const uint8_t *rleaf,
+                                                 const int *cb, double *out, Get get)
+{
+    for (int r = threadIdx.x; r < rows; r += kThreads) {
+        const int I = rleaf[r];
+        int c = upper && r > 0 ? r - 1 : 0;
+        int J = 0;
+        while (cb[J + 1] <= c) ++J;
+        double s = 0.0;
+        for (; c < cols; ++c) {
+            s += fabs(get(r, c));
+            if (c + 1 == cb[J + 1]) {
+                lds_max_nonneg(&out[I * kML + J], s);
+                s = 0.0;
+                ++J;
+            }
+        }
+    }
+}
+
+// e_IJ from the LDS state of the solved sources (see above).
+__device__ __forceinline__ int leaf_exponent(const SolveLds &L, int I, int J, int nla, double Tc)
+{
+    int emax = 0;
+    for (int K = I + 1; K < nla; ++K) emax = max(emax, L.eL[K * kML + J]);
+    for (int Lc = 0; Lc < J; ++Lc) emax = max(emax, L.eL[I * kML + Lc]);
+    // the bound times 2^-64 (every factor below 2^(1024-32), so nothing overflows)
+    double b = ldexp(L.nC[I * kML + J], -emax - 64);
+    for (int K = I + 1; K < nla; ++K)
+        b += ldexp(L.aN[I * kML + K], -32) * ldexp(L.nL[K * kML + J], L.eL[K * kML + J] - emax - 32);
+    for (int Lc = 0; Lc < J; ++Lc)
+        b += ldexp(L.nL[I * kML + Lc], L.eL[I * kML + Lc] - emax - 32) * ldexp(L.bN[Lc * kML + J], -32);
+    const double t = ldexp(Tc, -64);
+    int s = 0;
+    if (b > t) {
+        s = ilogb(b) - ilogb(t);
+        if (s < 0) s = 0;
+        while (ldexp(b, -s) > t) ++s;
+    }
+    return emax + s;
+}
+
+// As leaf_gemm, with the solved-tile operand (the A operand when scale_a, else the B operand)
+// multiplied on load by the exact power of two 2^(eL[kleaf[kbase + k] * mul + add] - e_t).
+__device__ __forceinline__ void leaf_gemm_scaled(d4 &acc, const double *Aop, int64_t lda, int nr,
+                                                 const double *Bop, int64_t ldb, int ncl, int k0, int k1,
+                                                 bool scale_a, const uint8_t *kleaf, int kbase, int mul,
+                                                 int add, const int *eL, int e_t)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    if (k0 >= k1) return;
+    const bool va = r < nr, vb = r < ncl;
+    const double *Ar = Aop + (va ? r : 0);
+    const double *Bc = Bop + (int64_t)(vb ? r : 0) * ldb;
+    for (int kc = k0; kc < k1; kc += 32) {
+        double af[8], bf[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc + 16 * (j >> 2) + 4 * q + (j & 3);
+            const int kk = k < k1 ? k : k0;
+            const int ex = eL[kleaf[kbase + kk] * mul + add] - e_t;
+            const double a = ldg(Ar + (int64_t)kk * lda), b = ldg(Bc + kk);
+            af[j] = scale_a ? ldexp(a, ex) : a;
+            bf[j] = scale_a ? b : ldexp(b, ex);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc + 16 * (j >> 2) + 4 * q + (j & 3);
+            const bool kin = k < k1;
+            acc = mfma16((vb && kin) ? bf[j] : 0.0, (va && kin) ? af[j] : 0.0, acc);
+        }
+    }
+}
+
+__device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *Bd, const DevView &Y,
+                                 double *S, int mr_, int nc_, double smin, double Tc, SolveLds &L)
+{
+    const int mr = uniform(mr_), nc = uniform(nc_);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (w == 0) leaf_offsets_wave(Ad, P.lda, mr, Bd, P.ldb, nc, L.la, L.lb, &L.nla, &L.nlb);
+    if (threadIdx.x == 0) L.fail = 0;
+    if (lane < 33) {                                 // zero row / column 16 of the leaf buffers
+        const int o = lane < 17 ? lane * kLd + 16 : 16 * kLd + (lane - 17);
+        L.leaf[w].R[o] = 0.0;
+        L.leaf[w].Al[o] = 0.0;
+        L.leaf[w].Bl[o] = 0.0;
+    }
+    for (int t = threadIdx.x; t < kML * kML; t += kThreads) {
+        L.eL[t] = 0;
+        L.nL[t] = 0.0;
+        L.nC[t] = 0.0;
+        L.aN[t] = 0.0;
+        L.bN[t] = 0.0;
+    }
+    __syncthreads();
+    const int nla = uniform(L.nla), nlb = uniform(L.nlb);
+    for (int r = threadIdx.x; r < mr; r += kThreads) {
+        int I = 0;
+        while (L.la[I + 1] <= r) ++I;
+        L.rowleaf[r] = (uint8_t)I;
+    }
+    for (int c = threadIdx.x; c < nc; c += kThreads) {
+        int J = 0;
+        while (L.lb[J + 1] <= c) ++J;
+        L.colleaf[c] = (uint8_t)J;
+    }
+    __syncthreads();
+    leaf_block_norms(mr, nc, false, L.rowleaf, L.lb, L.nC,
+                     [&](int r, int c) { return ld_dev(Y, (int64_t)c * P.ldc + r); });
+    leaf_block_norms(mr, mr, true, L.rowleaf, L.la, L.aN,
+                     [&](int r, int c) { return ldg(Ad + (int64_t)c * P.lda + r); });
+    leaf_block_norms(nc, nc, true, L.colleaf, L.lb, L.bN,
+                     [&](int r, int c) { return ldg(Bd + (int64_t)c * P.ldb + r); });
+    __syncthreads();
+    const int64_t lds = mr;
+    LeafLds &LL = L.leaf[w];
+    int ok = 1;
+    for (int d = 0; d < nla + nlb - 1; ++d) {
+        const int jlo = d - (nla - 1) > 0 ? d - (nla - 1) : 0;
+        const int jhi = d < nlb - 1 ? d : nlb - 1;
+        const int nleaf = jhi - jlo + 1;
+        const int parts = nleaf >= kWaves ? 1 : kWaves / nleaf;
+        double rhs[4];
+        if (w < nleaf) leaf_inputs(P, Ad, Bd, Y, L, LL, nla - 1 - (d - (jlo + w)), jlo + w, rhs);
+        // phase A: scaled partial right-hand-side GEMMs
+        for (int item = w; item < nleaf * parts; item += kWaves) {
+            const int J = jlo + item / parts, part = item % parts;
+            const int I = nla - 1 - (d - J);
+            const int e_t = leaf_exponent(L, I, J, nla, Tc);
+            const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
+            const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+            const int kb = L.la[I + 1];
+            const int K1 = mr - kb, K2 = lc0;
+            const int nch = (K1 + 15) / 16 + (K2 + 15) / 16;
+            const int c0 = (int)(((int64_t)part * nch) / parts), c1 = (int)(((int64_t)(part + 1) * nch) / parts);
+            const int n1 = (K1 + 15) / 16;
+            d4 acc = zero4();
+            if (c0 < n1)       // A(I, below) (2^(e_KJ - e) Y(below, J)): row leaf K of source row kb + k
+                leaf_gemm_scaled(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
+                                 lds, ncl, 16 * c0, c1 < n1 ? 16 * c1 : K1, false, L.rowleaf, kb, kML, J,
+                                 L.eL, e_t);
+            if (c1 > n1) {     // (2^(e_IL - e) Y(I, left)) B(left, J): column leaf of source column k
+                const int s0 = (c0 > n1 ? c0 : n1) - n1, s1 = c1 - n1;
+                leaf_gemm_scaled(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 16 * s0,
+                                 16 * s1 < K2 ? 16 * s1 : K2, true, L.colleaf, 0, 1, I * kML, L.eL, e_t);
+            }
+            double *pp = L.part[item];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pp[((lane >> 4) + 4 * i) * kLd + (lane & 15)] = acc[i];
+        }
+        __syncthreads();
+        // phase B: each wave fills, solves (with power-of-two retries) and stores its leaves
+        for (int li = w; li < nleaf; li += kWaves) {
+            const int J = jlo + li, I = nla - 1 - (d - J);
+            if (li >= kWaves) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
+            int e = leaf_exponent(L, I, J, nla, Tc);
+            const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
+            const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+            double v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                v[i] = 0.0;
+                if (mm < nr && nn < ncl) {
+                    double g = 0.0;
+                    for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
+                    v[i] = ldexp(rhs[i], -e) - g;
+                    if (!(fabs(v[i]) <= Tc)) ok = 0;
+                }
+                LL.R[nn * kLd + mm] = v[i];
+            }
+            wave_sync_lds();
+            const LeafMasks M = leaf_masks(LL, nr, ncl);
+            if (!leaf_setup(LL, M, smin)) ok = 0;
+            int t = 0;
+            bool done = false, blind = false;
+            for (int attempt = 0; attempt < 8 && uniform(__all(ok)); ++attempt) {
+                double vm;
+                if (!leaf_solve(LL, nr, ncl, smin, Tc, M, &vm)) ok = 0;
+                vm = wave_max(vm);
+                if (vm <= Tc) {
+                    // after a blind shift (the previous try overflowed), move the largest value
+                    // back up to about Tc / 4 so the leaf is not scaled further than needed
+                    const int gap = vm > 0.0 ? ilogb(Tc) - ilogb(vm) - 2 : 0;
+                    if (!(blind && gap > 8)) { done = true; break; }
+                    blind = false;
+                    t -= gap;
+                } else {
+                    // linear in the right-hand side: shift it so the largest value lands below
+                    // Tc / 2; an overflowed try gives no magnitude, so shift blindly
+                    blind = !(vm <= 0x1.fffffffffffffp+1023);
+                    t += blind ? 256 : max(1, ilogb(vm) - ilogb(Tc) + 2);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                    LL.R[nn * kLd + mm] = ldexp(v[i], -t);
+                }
+                wave_sync_lds();
+            }
+            if (!done) ok = 0;
+            e += t;
+            // the leaf's infinity norm
+            double rs = 0.0;
+            if (lane < nr)
+                for (int cc = 0; cc < ncl; ++cc) rs += fabs(LL.R[cc * kLd + lane]);
+            rs = wave_max(rs);
+            if (lane == 0) {
+                L.eL[I * kML + J] = e;
+                L.nL[I * kML + J] = rs;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
+                if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
+            }
+        }
+        if (!ok) L.fail = 1;
+        __threadfence_block();
+        __syncthreads();
+        if (uniform(L.fail)) break;
+    }
+    __syncthreads();
+    if (uniform(L.fail)) return -1;
+    // consistency: every leaf to the largest exponent
+    int et = 0;
+    for (int I = 0; I < nla; ++I)
+        for (int J = 0; J < nlb; ++J) et = max(et, L.eL[I * kML + J]);
+    et = uniform(et);
+    for (int t = threadIdx.x; t < mr * nc; t += kThreads) {
+        const int rr = t % mr, cc = t / mr;
+        const int ex = L.eL[L.rowleaf[rr] * kML + L.colleaf[cc]] - et;
+        if (ex != 0) {
+            double *p = S + (int64_t)cc * lds + rr;
+            stg(p, ldexp(ldg(p), ex));
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    return et;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -480,8 +759,17 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         if (!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016)
             done = uniform(tile_solve_fast(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));
         TRSYL_STAMP(stamp, 2);
+        if (!done && !(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016) {
+            // the leaf-tiled robust solve (the fast path left Y untouched)
+            if (threadIdx.x == 0) atomicAdd(&P.stats[2], 1u);
+            const int es = uniform(tile_solve_scaled(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L));
+            if (es >= 0) {
+                e_syl = es;
+                done = 1;
+            }
+        }
         if (!done) {
-            // Algorithm 2 on a private copy of the tile (the fast path left Y untouched)
+            // Algorithm 2 on a private copy of the tile (the fast paths left Y untouched)
             if (threadIdx.x == 0) atomicAdd(&P.stats[0], 1u);
             for (int t = threadIdx.x; t < mr * nc; t += kThreads) {
                 const int rr = t % mr, cc = t / mr;
