@@ -119,12 +119,19 @@ def paper_sweeps(args):
     points = [("no scaling (mu = m, nu = n)", int(s), None, None) for s in args.paper_sizes.split(",") if s]
     points += [("cost of robustness (nu = 1e-2)", args.paper_robust_size, mu, 1e-2)
                for mu in (1e2, 10.0, 1.0, 1e-3, 1e-7)]
+    points += [("growth workload (lambda_A U[-1,1] 1e-2, |lambda_A + lambda_B| in [1e-3, 1e-2] on the "
+                "paired diagonal, strict upper U[-10,10])", 4096, None, None)]
     L = T.lib()
     for (kind, m, mu, nu) in points:
         mu_v = float(m) if mu is None else mu
         nu_v = float(m) if nu is None else nu
-        print(f"[paper] m=n={m} mu={mu_v:g} nu={nu_v:g}: generating", file=sys.stderr, flush=True)
-        A_np, B_np, C_np = W.paper_problem(args.seed, m, m, mu_v, nu_v, p2x2=0.1)
+        growth = kind.startswith("growth")
+        print(f"[paper] {kind[:20]} m=n={m}: generating", file=sys.stderr, flush=True)
+        if growth:
+            A_np, B_np, C_np = W.config_growth(args.seed, m, m)
+            mu_v = nu_v = None
+        else:
+            A_np, B_np, C_np = W.paper_problem(args.seed, m, m, mu_v, nu_v, p2x2=0.1)
         Ac, Bc, C0 = T.colmajor(A_np, dev), T.colmajor(B_np, dev), T.colmajor(C_np, dev)
         del A_np, B_np
         opts = T.make_opts()
@@ -156,8 +163,9 @@ def paper_sweeps(args):
         resid = residual_lib(T, Ac, Bc, Yc, e_t, C0, m, m)
         c = cnt.cpu().tolist()
         t = statistics.median(times)
-        print(json.dumps({"workload": "paper test matrices", "points": kind, "m": m, "n": m, "mu": mu_v,
-                          "nu": nu_v, "p2x2": 0.1, "ms_median": round(1e3 * t, 3),
+        print(json.dumps({"workload": "growth" if growth else "paper test matrices", "points": kind, "m": m,
+                          "n": m, "mu": mu_v, "nu": nu_v, "p2x2": 0.0 if growth else 0.1,
+                          "ms_median": round(1e3 * t, 3),
                           "gflops": round(W.flop_count(m, m) / t / 1e9, 2), "scale_log2": e,
                           "info": int(info_t.item()), "leaf_tiled_tile_solves": c[2],
                           "fallback_tile_solves": c[0], "scaled_tile_updates": c[1], "residual_eq9": resid,
