@@ -140,15 +140,18 @@ int trsyl_grad(int64_t m, int64_t n, const double *A, int64_t lda, const double 
 /*
  * Batched robust solve: `count` independent problems of arbitrary sizes (rectangular allowed) in
  * one launch per stage -- structure, bounds, one persistent tile-DAG kernel over the merged task
- * lists of all problems, finalisation and consistency scaling (the forward FP64 form, Algorithm 4
- * per problem).
+ * lists of all problems, finalisation and consistency scaling (Algorithm 4 per problem).  With
+ * opts->precision = TRSYL_FP32_REFINE the batch runs the precision form: one batched solve with
+ * FP32-MFMA tile updates, then opts->max_sweeps sweeps that form each problem's FP64 residual,
+ * solve all corrections in one batched solve and update every problem.
  *   m, n, lda, ldb, ldc   host arrays [count]
  *   A, B, C               host arrays [count] of device pointers (as in trsyl_robust)
  *   tiles                 host array [2 * count] of (tile_m, tile_n) per problem, e.g. from an
  *                         autotuner; NULL = opts->tile_m / tile_n for every problem
  *   scale_log2, scale, info   device arrays [count] (scale may be NULL)
  *   workspace             >= trsyl_batched_workspace_size(count, m, n, tiles, opts), 256-aligned
- * A problem's results are identical to trsyl_robust's with the same tile sizes.  The return value
+ * A problem's results are identical to trsyl_robust's with the same tile sizes and options.  The
+ * return value
  * is the host argument check only (negative: argument index); per-problem status goes to info[i].
  */
 size_t trsyl_batched_workspace_size(int32_t count, const int64_t *m, const int64_t *n,

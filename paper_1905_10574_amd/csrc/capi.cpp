@@ -402,6 +402,12 @@ struct BLayout {
     size_t plans = 0, offs = 0, ticket = 0, regions_begin = 0, regions_end = 0, scratch = 0,
            tasks = 0, tprob = 0, total = 0;
     int64_t ntasks = 0;
+    // precision form: per problem C0 (the original C) and D (the correction), each m x n
+    // column-major; then shared norm partials and per-problem sweep scalars
+    bool refine = false;
+    int max_sweeps = 0;
+    std::vector<size_t> c0, d;
+    size_t part = 0, eD = 0, negsy = 0, infoD = 0, sy = 0, tY = 0, sD = 0;
 };
 
 // Returns 0 or the negative argument index that is invalid.
@@ -414,7 +420,8 @@ int make_blayout(int32_t count, const int64_t *m, const int64_t *n, const int32_
     B->region.resize(count);
     Resolved base;
     if (int e = resolve(opts, &base, 14)) return e;
-    if (base.precision != TRSYL_FP64) return -14;    // batched solves run the FP64 form
+    B->refine = base.precision == TRSYL_FP32_REFINE;
+    B->max_sweeps = base.max_sweeps;
     B->workers = base.workers ? base.workers : device_cus();
     size_t o = 0;
     B->plans = o; o = align_up(o + sizeof(Plan) * (size_t)count);
@@ -441,6 +448,22 @@ int make_blayout(int32_t count, const int64_t *m, const int64_t *n, const int32_
     B->scratch = o; o = align_up(o + 8 * (size_t)B->workers * kMaxTile * kMaxTile);
     B->tasks = o; o = align_up(o + 8 * (size_t)B->ntasks);
     B->tprob = o; o = align_up(o + 4 * (size_t)B->ntasks);
+    if (B->refine) {
+        B->c0.resize(count);
+        B->d.resize(count);
+        for (int p = 0; p < count; ++p) {
+            const size_t mn = 8 * (size_t)m[p] * (size_t)n[p];
+            B->c0[p] = o; o = align_up(o + mn);
+            B->d[p] = o; o = align_up(o + mn);
+        }
+        B->part = o; o = align_up(o + 8 * (size_t)kNormParts);
+        B->eD = o; o = align_up(o + 8 * (size_t)count);
+        B->negsy = o; o = align_up(o + 8 * (size_t)count);
+        B->infoD = o; o = align_up(o + 4 * (size_t)count);
+        B->sy = o; o = align_up(o + 4 * (size_t)count);
+        B->tY = o; o = align_up(o + 8 * (size_t)count);
+        B->sD = o; o = align_up(o + 4 * (size_t)count);
+    }
     B->total = o;
     return 0;
 }
@@ -499,6 +522,147 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
     if (k != B.ntasks) { hipHostFree(mt->pinned); delete mt; return nullptr; }
     cache[key] = mt;
     return mt;
+}
+
+// One batched solve over the layout BL (plans rebuilt for the given C, scale and info arrays).
+int batched_core(const BLayout &BL, int32_t count, const int64_t *m, const int64_t *n, const double *const *A,
+                 const int64_t *lda, const double *const *B, const int64_t *ldb, double *const *C,
+                 const int64_t *ldc, int64_t *scale_log2, double *scale, int32_t *info, int extra_flags,
+                 char *ws, hipEvent_t *ev, hipStream_t stream)
+{
+    // host images of the plans and the stage offset tables
+    std::vector<Plan> plans(count);
+    std::vector<int32_t> offs(5 * (size_t)(count + 1), 0);
+    int32_t *oS = offs.data(), *oA = oS + (count + 1), *oB = oA + (count + 1), *oC = oB + (count + 1),
+            *oK = oC + (count + 1);
+    for (int p = 0; p < count; ++p) {
+        const Layout &L = BL.L[p];
+        Resolved rp = BL.r[p];
+        rp.flags |= extra_flags;
+        Plan P = make_plan(m[p], n[p], A[p], lda[p], B[p], ldb[p], C[p], ldc[p], rp, L, ws + BL.region[p]);
+        P.pt = L.pt; P.qt = L.qt;
+        P.tasks = nullptr; P.ntasks = 0;
+        P.scratch = (double *)(ws + BL.scratch);
+        P.ticket = (uint32_t *)(ws + BL.ticket);
+        P.e_out = scale_log2 + p;
+        P.scale_out = scale ? scale + p : nullptr;
+        P.info_out = info + p;
+        P.trace = nullptr;
+        plans[p] = P;
+        const int64_t items = std::max(m[p], n[p]) + 2;
+        const int gS = (L.pt && L.qt) ? (int)std::min<int64_t>((items + 255) / 256, 64) : 0;
+        oS[p + 1] = oS[p] + gS;
+        oA[p + 1] = oA[p] + ((L.pt && L.qt) ? L.pt * L.pt : 0);
+        oB[p + 1] = oB[p] + ((L.pt && L.qt) ? L.qt * L.qt : 0);
+        oC[p + 1] = oC[p] + L.pt * L.qt;
+        oK[p + 1] = oK[p] + ((L.pt && L.qt) ? consistency_per_tile(BL.r[p].tm, BL.r[p].tn) * L.pt * L.qt : 0);
+    }
+    const MergedTasks *mt = get_merged(BL, m, n);
+    if (!mt) return -100;
+    if (launch_fill_zero(ws + BL.ticket, BL.regions_end - BL.ticket, stream) != hipSuccess) return -100;
+    if (hipMemcpyAsync(ws + BL.plans, plans.data(), sizeof(Plan) * (size_t)count, hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+        return -100;
+    if (hipMemcpyAsync(ws + BL.offs, offs.data(), 4 * offs.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return -100;
+    if (BL.ntasks > 0) {
+        if (hipMemcpyAsync(ws + BL.tasks, mt->pinned, 8 * (size_t)BL.ntasks, hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(ws + BL.tprob, mt->pinned + BL.ntasks, 4 * (size_t)BL.ntasks, hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return -100;
+    }
+    BatchedLaunch bl{};
+    bl.count = count;
+    bl.plans = (const Plan *)(ws + BL.plans);
+    const int32_t *dof = (const int32_t *)(ws + BL.offs);
+    bl.off_structure = dof;
+    bl.off_A = dof + (count + 1);
+    bl.off_B = dof + 2 * (count + 1);
+    bl.off_C = dof + 3 * (count + 1);
+    bl.off_consistency = dof + 4 * (count + 1);
+    bl.blocks_structure = oS[count];
+    bl.blocks_bounds = oA[count] + oB[count] + oC[count];
+    bl.blocks_consistency = oK[count];
+    bl.tasks = (const uint64_t *)(ws + BL.tasks);
+    bl.tprob = (const uint32_t *)(ws + BL.tprob);
+    bl.ntasks = BL.ntasks;
+    bl.ticket = (uint32_t *)(ws + BL.ticket);
+    bl.scratch = (double *)(ws + BL.scratch);
+    bl.workers = BL.workers;
+    if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
+    if (launch_batched(bl, stream) != hipSuccess) return -100;
+    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
+    return 0;
+}
+
+// The precision form over a batch: the batched FP32-update solve, then max_sweeps sweeps, each
+// forming every problem's FP64 residual (as in solve_refined), solving all corrections in one
+// batched FP32-update solve, and updating every problem.  Per problem the launches and their
+// order match solve_refined's, so each result equals the single solve's with the same tiles.
+int batched_refined(const BLayout &BL, int32_t count, const int64_t *m, const int64_t *n,
+                    const double *const *A, const int64_t *lda, const double *const *B, const int64_t *ldb,
+                    double *const *C, const int64_t *ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                    char *ws, hipEvent_t *ev, hipStream_t stream)
+{
+    std::vector<double *> Dp(count);
+    std::vector<int64_t> ldd(count);
+    for (int p = 0; p < count; ++p) {
+        Dp[p] = (double *)(ws + BL.d[p]);
+        ldd[p] = std::max<int64_t>(1, m[p]);
+        if (m[p] > 0 && n[p] > 0 &&
+            hipMemcpy2DAsync(ws + BL.c0[p], 8 * (size_t)m[p], C[p], 8 * (size_t)ldc[p], 8 * (size_t)m[p],
+                             (size_t)n[p], hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return -100;
+    }
+    if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
+    int rcode = batched_core(BL, count, m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, kFlagF32Updates,
+                             ws, nullptr, stream);
+    if (rcode) return rcode;
+    double *part = (double *)(ws + BL.part);
+    int64_t *eD = (int64_t *)(ws + BL.eD), *negsy = (int64_t *)(ws + BL.negsy);
+    int32_t *infoD = (int32_t *)(ws + BL.infoD), *sy = (int32_t *)(ws + BL.sy), *sD = (int32_t *)(ws + BL.sD);
+    double *tY = (double *)(ws + BL.tY);
+    for (int sweep = 0; sweep < BL.max_sweeps; ++sweep) {
+        for (int p = 0; p < count; ++p) {
+            if (m[p] == 0 || n[p] == 0) continue;
+            const int mi = (int)m[p], ni = (int)n[p];
+            if (launch_norm(C[p], ldc[p], mi, ni, 0, part, sy + p, tY + p, stream) != hipSuccess) return -100;
+            if (launch_neg_exp(sy + p, negsy + p, stream) != hipSuccess) return -100;
+            GemmDesc g{};
+            g.M = mi; g.N = ni; g.K = mi;                 // D = 2^(-e-sy) C0 - 2^-sy A Y
+            g.A = A[p]; g.sAm = 1; g.sAk = lda[p]; g.triA = 1;
+            g.B = C[p]; g.sBk = 1; g.sBn = ldc[p]; g.triB = 0;
+            g.Cin = (const double *)(ws + BL.c0[p]); g.ldcin = mi;
+            g.Out = Dp[p]; g.ldo = mi;
+            g.sa1 = 0; g.sb1 = 1;
+            g.asign = -1.0; g.ae0 = 0; g.ae1 = 0; g.ae2 = 0;
+            g.csign = 1.0; g.ce0 = 0; g.ce1 = 1; g.ce2 = -1;
+            g.ep1 = negsy + p; g.ep2 = scale_log2 + p;
+            g.mask = 0; g.pat = nullptr; g.ldpat = 1;
+            if (launch_gemm(g, stream) != hipSuccess) return -100;
+            g.K = ni;                                     // D -= 2^-sy Y B
+            g.A = C[p]; g.sAm = 1; g.sAk = ldc[p]; g.triA = 0;
+            g.B = B[p]; g.sBk = 1; g.sBn = ldb[p]; g.triB = 1;
+            g.sa1 = 1; g.sb1 = 0;
+            g.Cin = Dp[p]; g.ldcin = mi;
+            g.ce1 = 0; g.ce2 = 0;
+            if (launch_gemm(g, stream) != hipSuccess) return -100;
+        }
+        rcode = batched_core(BL, count, m, n, A, lda, B, ldb, Dp.data(), ldd.data(), eD, nullptr, infoD,
+                             kFlagF32Updates, ws, nullptr, stream);
+        if (rcode) return rcode;
+        for (int p = 0; p < count; ++p) {
+            if (m[p] == 0 || n[p] == 0) continue;
+            const int mi = (int)m[p], ni = (int)n[p];
+            if (launch_absmax_exp(Dp[p], mi, mi, ni, part, sD + p, stream) != hipSuccess) return -100;
+            if (launch_refine_update(C[p], ldc[p], Dp[p], mi, mi, ni, eD + p, negsy + p, sD + p, scale_log2 + p,
+                                     info + p, infoD + p, scale ? scale + p : nullptr, stream) != hipSuccess)
+                return -100;
+        }
+    }
+    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
+    return 0;
 }
 
 }  // namespace
@@ -612,69 +776,10 @@ int trsyl_robust_batched(int32_t count, const int64_t *m, const int64_t *n, cons
     if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -15;
     if (ws_bytes < BL.total) return -16;
     char *ws = (char *)workspace;
-    // host images of the plans and the stage offset tables
-    std::vector<Plan> plans(count);
-    std::vector<int32_t> offs(5 * (size_t)(count + 1), 0);
-    int32_t *oS = offs.data(), *oA = oS + (count + 1), *oB = oA + (count + 1), *oC = oB + (count + 1),
-            *oK = oC + (count + 1);
-    for (int p = 0; p < count; ++p) {
-        const Layout &L = BL.L[p];
-        Plan P = make_plan(m[p], n[p], A[p], lda[p], B[p], ldb[p], C[p], ldc[p], BL.r[p], L, ws + BL.region[p]);
-        P.pt = L.pt; P.qt = L.qt;
-        P.tasks = nullptr; P.ntasks = 0;
-        P.scratch = (double *)(ws + BL.scratch);
-        P.ticket = (uint32_t *)(ws + BL.ticket);
-        P.e_out = scale_log2 + p;
-        P.scale_out = scale ? scale + p : nullptr;
-        P.info_out = info + p;
-        P.trace = nullptr;
-        plans[p] = P;
-        const int64_t items = std::max(m[p], n[p]) + 2;
-        const int gS = (L.pt && L.qt) ? (int)std::min<int64_t>((items + 255) / 256, 64) : 0;
-        oS[p + 1] = oS[p] + gS;
-        oA[p + 1] = oA[p] + ((L.pt && L.qt) ? L.pt * L.pt : 0);
-        oB[p + 1] = oB[p] + ((L.pt && L.qt) ? L.qt * L.qt : 0);
-        oC[p + 1] = oC[p] + L.pt * L.qt;
-        oK[p + 1] = oK[p] + ((L.pt && L.qt) ? consistency_per_tile(BL.r[p].tm, BL.r[p].tn) * L.pt * L.qt : 0);
-    }
-    const MergedTasks *mt = get_merged(BL, m, n);
-    if (!mt) return -100;
-    if (launch_fill_zero(ws + BL.ticket, BL.regions_end - BL.ticket, stream) != hipSuccess) return -100;
-    if (hipMemcpyAsync(ws + BL.plans, plans.data(), sizeof(Plan) * (size_t)count, hipMemcpyHostToDevice,
-                       stream) != hipSuccess)
-        return -100;
-    if (hipMemcpyAsync(ws + BL.offs, offs.data(), 4 * offs.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
-        return -100;
-    if (BL.ntasks > 0) {
-        if (hipMemcpyAsync(ws + BL.tasks, mt->pinned, 8 * (size_t)BL.ntasks, hipMemcpyHostToDevice, stream) !=
-                hipSuccess ||
-            hipMemcpyAsync(ws + BL.tprob, mt->pinned + BL.ntasks, 4 * (size_t)BL.ntasks, hipMemcpyHostToDevice,
-                           stream) != hipSuccess)
-            return -100;
-    }
-    BatchedLaunch bl{};
-    bl.count = count;
-    bl.plans = (const Plan *)(ws + BL.plans);
-    const int32_t *dof = (const int32_t *)(ws + BL.offs);
-    bl.off_structure = dof;
-    bl.off_A = dof + (count + 1);
-    bl.off_B = dof + 2 * (count + 1);
-    bl.off_C = dof + 3 * (count + 1);
-    bl.off_consistency = dof + 4 * (count + 1);
-    bl.blocks_structure = oS[count];
-    bl.blocks_bounds = oA[count] + oB[count] + oC[count];
-    bl.blocks_consistency = oK[count];
-    bl.tasks = (const uint64_t *)(ws + BL.tasks);
-    bl.tprob = (const uint32_t *)(ws + BL.tprob);
-    bl.ntasks = BL.ntasks;
-    bl.ticket = (uint32_t *)(ws + BL.ticket);
-    bl.scratch = (double *)(ws + BL.scratch);
-    bl.workers = BL.workers;
     hipEvent_t *ev = opts ? (hipEvent_t *)opts->profile_events : nullptr;
-    if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return -100;
-    if (launch_batched(bl, stream) != hipSuccess) return -100;
-    if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
-    return 0;
+    if (!BL.refine)
+        return batched_core(BL, count, m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, 0, ws, ev, stream);
+    return batched_refined(BL, count, m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, ws, ev, stream);
 }
 
 }  // extern "C"

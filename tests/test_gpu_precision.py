@@ -43,3 +43,32 @@ def test_fp32_refine_growth(T):
     Yn = Y.cpu().numpy()
     assert np.all(np.isfinite(Yn)) and np.abs(Yn).max() <= 2.0 ** 1022
     assert T.residual(A, B, Y, e, C) <= 1e-12
+
+
+def test_fp32_refine_batched_matches_single(T):
+    """The batched precision form: each problem's result is bit-identical to the single solve's
+    with the same tiles and sweeps (same kernels in the same order per problem), and satisfies
+    eq. (9) <= 1e-12; a growth problem in the batch stays robust; empty problems pass through."""
+    shapes = [(130, 97), (64, 200), (0, 5), (257, 129), (90, 90)]
+    probs = []
+    for i, (m, n) in enumerate(shapes):
+        if m == 0 or n == 0:
+            probs.append((np.eye(m), np.eye(n), np.zeros((m, n))))
+        elif i == 3:
+            probs.append(W.growth_problem(7, m, n))
+        else:
+            probs.append(W.separated_problem(50 + i, m, n))
+    tiles = [(64, 32), (32, 64), (16, 16), (64, 64), (48, 48)]
+    out = T.solve_batched([p[0] for p in probs], [p[1] for p in probs], [p[2] for p in probs], tiles,
+                          precision="fp32_refine", max_sweeps=2)
+    for i, ((A, B, C), (tm, tn), (Y, e, info)) in enumerate(zip(probs, tiles, out)):
+        m, n = C.shape
+        print(f"  problem {i}: m={m} n={n} e={e} info={info}", flush=True)
+        Ys, es, infos = T.solve(A, B, C, tile=tm, tile_n=tn, precision="fp32_refine", max_sweeps=2)
+        assert e == es and info == infos
+        assert torch.equal(Y.cpu(), Ys.cpu())
+        if m and n:
+            assert info == 0
+            assert T.residual(A, B, Y, e, C) <= 1e-12
+            if i == 3:
+                assert e > 0
