@@ -174,6 +174,104 @@ def paper_sweeps(args):
         torch.cuda.empty_cache()
 
 
+def _dev_views(T, X, dev):
+    """A device view of X whose transposed storage is the column-major buffer (the binding then
+    uses it without copying)."""
+    return T.colmajor(X, dev).t()
+
+
+def batched_bench(args):
+    """The batched workload: one batched solve (FP64, then FP32+refine with --sweeps sweeps) of the
+    256-problem set, tiles from the autotuner; aggregate GFLOP/s = sum F_i / t (median of 3 timed
+    batches after one warm-up, inputs resident, host wall clock around the synchronised call)."""
+    import statistics
+    import torch
+    import paper_1905_10574_amd as T
+    import trsyl_workloads as W
+
+    dev = torch.device("cuda:0")
+    probs = W.config_batched(args.seed)
+    As = [_dev_views(T, p[1], dev) for p in probs]
+    Bs = [_dev_views(T, p[2], dev) for p in probs]
+    C0 = [_dev_views(T, p[3], dev) for p in probs]
+    flops = sum(W.flop_count(*p[3].shape) for p in probs)
+    print(f"[batched] {len(probs)} problems, sum F = {flops:.4g}; autotuning tiles", file=sys.stderr, flush=True)
+    table = T.autotune_tiles()
+    tiles = [(T.tile_for(C.shape[0]), T.tile_for(C.shape[1])) for C in C0]
+    for label, kw in (("fp64", {}), ("fp32_refine", {"precision": "fp32_refine", "max_sweeps": args.sweeps})):
+        opts = T.make_opts(**kw)
+        times = []
+        for rep in range(4):
+            Cs = [C.clone() for C in C0]
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            Ycs, e, info = T.solve_batched_async(As, Bs, Cs, tiles, opts)
+            torch.cuda.synchronize(dev)
+            dt = time.perf_counter() - t0
+            print(f"[batched] {label} batch {rep}: {1e3 * dt:.2f} ms", file=sys.stderr, flush=True)
+            if rep:
+                times.append(dt)
+        es, infos = e.cpu().tolist(), info.cpu().tolist()
+        worst = 0.0
+        for i, p in enumerate(probs):
+            m, n = p[3].shape
+            if m and n:
+                et = torch.tensor([es[i]], dtype=torch.int64, device=dev)
+                worst = max(worst, residual_lib(T, As[i].t(), Bs[i].t(), Ycs[i], et, C0[i].t(), m, n))
+        t = statistics.median(times)
+        print(json.dumps({"workload": "batched: 256 problems, m, n log-uniform [64, 2048], half separated, "
+                                      "half growth", "form": label, "problems": len(probs),
+                          "sum_flops": flops, "ms_median": round(1e3 * t, 3),
+                          "gflops": round(flops / t / 1e9, 2), "max_residual_eq9": worst,
+                          "max_info": max(infos), "growth_problems_scaled": sum(1 for i, p in enumerate(probs)
+                                                                                if p[0] == "growth" and es[i] > 0),
+                          "tile_table": {str(k): v for k, v in table.items()}}), flush=True)
+
+
+def adjoint_bench(args):
+    """The adjoint workload: for each of 32 problems the forward solve, the adjoint solve and the
+    gradient products, all enqueued on one stream; GFLOP/s counts F_fwd + 2 F_fwd per problem
+    (median of 3 timed passes after one warm-up)."""
+    import statistics
+    import torch
+    import paper_1905_10574_amd as T
+    import trsyl_workloads as W
+
+    dev = torch.device("cuda:0")
+    probs = W.config_adjoint(args.seed)
+    As = [_dev_views(T, p[0], dev) for p in probs]
+    Bs = [_dev_views(T, p[1], dev) for p in probs]
+    C0 = [_dev_views(T, p[2], dev) for p in probs]
+    W0 = [_dev_views(T, p[3], dev) for p in probs]
+    fwd = sum(W.flop_count(*p[2].shape) for p in probs)
+    opts = T.make_opts()
+    times, tf, tb = [], [], []
+    for rep in range(4):
+        Cs = [C.clone() for C in C0]
+        Ws = [Wm.clone() for Wm in W0]
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        outs = [T.solve_async(A, B, C, opts) for A, B, C in zip(As, Bs, Cs)]
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        grads = []
+        for A, B, Wm, (Ys, e, sc, info) in zip(As, Bs, Ws, outs):
+            Gs, eG, infoG = T.adjoint_async(A, B, Wm, opts)
+            grads.append(T.grad(A, B, Ys.t(), e, Gs.t(), eG))
+        torch.cuda.synchronize(dev)
+        t2 = time.perf_counter()
+        print(f"[adjoint] pass {rep}: forward {1e3 * (t1 - t0):.2f} ms, backward {1e3 * (t2 - t1):.2f} ms",
+              file=sys.stderr, flush=True)
+        if rep:
+            times.append(t2 - t0); tf.append(t1 - t0); tb.append(t2 - t1)
+    t = statistics.median(times)
+    print(json.dumps({"workload": "adjoint: 32 problems, m, n uniform in [256, 1536], separated",
+                      "forward_flops": fwd, "counted_flops": 3 * fwd, "ms_median": round(1e3 * t, 3),
+                      "forward_ms_median": round(1e3 * statistics.median(tf), 3),
+                      "backward_ms_median": round(1e3 * statistics.median(tb), 3),
+                      "gflops": round(3 * fwd / t / 1e9, 2)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +294,12 @@ def main():
     ap.add_argument("--paper-sizes", default="1000,2000,10000,20000")
     ap.add_argument("--paper-robust-size", type=int, default=10000)
     ap.add_argument("--paper-reps", type=int, default=3, help="timed solves per point (median)")
+    ap.add_argument("--batched", action="store_true",
+                    help="time the batched workload instead (256 problems, m, n log-uniform in [64, 2048], "
+                         "half separated and half growth; autotuned tiles; FP64 and FP32+refine)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint workload instead (32 problems, m, n uniform in [256, 1536]: "
+                         "forward solve, adjoint solve and gradient products)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run three plain device-to-device copies of BYTES bytes (the reference "
                          "kernel that scales the HBM byte counters) and exit")
@@ -214,6 +318,10 @@ def main():
 
     if args.paper:
         return paper_sweeps(args)
+    if args.batched:
+        return batched_bench(args)
+    if args.adjoint:
+        return adjoint_bench(args)
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
