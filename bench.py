@@ -229,9 +229,10 @@ def batched_bench(args):
 
 
 def adjoint_bench(args):
-    """The adjoint workload: for each of 32 problems the forward solve, the adjoint solve and the
-    gradient products, all enqueued on one stream; GFLOP/s counts F_fwd + 2 F_fwd per problem
-    (median of 3 timed passes after one warm-up)."""
+    """The adjoint workload: the 32 forward solves in one batched solve, the 32 adjoint solves in
+    one batched adjoint solve, then each problem's gradient products (three masked / scaled MFMA
+    products); GFLOP/s counts F_fwd + 2 F_fwd per problem (median of 3 timed passes after one
+    warm-up, host wall clock around stream-synchronised phases)."""
     import statistics
     import torch
     import paper_1905_10574_amd as T
@@ -246,30 +247,40 @@ def adjoint_bench(args):
     fwd = sum(W.flop_count(*p[2].shape) for p in probs)
     opts = T.make_opts()
     times, tf, tb = [], [], []
+    worst = 0.0
     for rep in range(4):
         Cs = [C.clone() for C in C0]
         Ws = [Wm.clone() for Wm in W0]
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        outs = [T.solve_async(A, B, C, opts) for A, B, C in zip(As, Bs, Cs)]
+        Ys, eY, infoY = T.solve_batched_async(As, Bs, Cs, None, opts)
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
-        grads = []
-        for A, B, Wm, (Ys, e, sc, info) in zip(As, Bs, Ws, outs):
-            Gs, eG, infoG = T.adjoint_async(A, B, Wm, opts)
-            grads.append(T.grad(A, B, Ys.t(), e, Gs.t(), eG))
+        Gs, eG, infoG = T.adjoint_batched_async(As, Bs, Ws, None, opts)
+        grads = [T.grad(A, B, Y.t(), eY[i:i + 1], G.t(), eG[i:i + 1])
+                 for i, (A, B, Y, G) in enumerate(zip(As, Bs, Ys, Gs))]
         torch.cuda.synchronize(dev)
         t2 = time.perf_counter()
         print(f"[adjoint] pass {rep}: forward {1e3 * (t1 - t0):.2f} ms, backward {1e3 * (t2 - t1):.2f} ms",
               file=sys.stderr, flush=True)
         if rep:
             times.append(t2 - t0); tf.append(t1 - t0); tb.append(t2 - t1)
+    # adjoint residual check: A^T G + G B^T = 2^-eG W (outside the timed region)
+    eGl = eG.cpu().tolist()
+    for i, p in enumerate(probs):
+        A, B, Wm = p[0], p[1], p[3]
+        G = Gs[i].t().cpu().numpy()
+        R = A.T @ G + G @ B.T - np.ldexp(Wm, -eGl[i])
+        q = np.linalg.norm(R) / ((np.linalg.norm(A) + np.linalg.norm(B)) * np.linalg.norm(G) +
+                                 np.linalg.norm(np.ldexp(Wm, -eGl[i])))
+        worst = max(worst, float(q))
     t = statistics.median(times)
     print(json.dumps({"workload": "adjoint: 32 problems, m, n uniform in [256, 1536], separated",
                       "forward_flops": fwd, "counted_flops": 3 * fwd, "ms_median": round(1e3 * t, 3),
                       "forward_ms_median": round(1e3 * statistics.median(tf), 3),
                       "backward_ms_median": round(1e3 * statistics.median(tb), 3),
-                      "gflops": round(3 * fwd / t / 1e9, 2)}), flush=True)
+                      "gflops": round(3 * fwd / t / 1e9, 2), "max_adjoint_residual": worst,
+                      "max_info": max(infoY.cpu().tolist() + infoG.cpu().tolist())}), flush=True)
 
 
 def main():

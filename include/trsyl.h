@@ -124,6 +124,23 @@ int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, con
                          trsyl_stream_t stream);
 
 /*
+ * Batched adjoint solve: `count` independent problems A_i^T G_i + G_i B_i^T = alpha_i W_i (the
+ * transposed problems of Sec. 8's gradient derivation), each reversed as in trsyl_robust_adjoint
+ * and all solved by one batched forward solve (trsyl_robust_batched).  Arguments as in
+ * trsyl_robust_batched, with W (in: W_i, out: G_i) in place of C; workspace >=
+ * trsyl_adjoint_batched_workspace_size(count, m, n, tiles, opts).  A problem's results are
+ * identical to trsyl_robust_adjoint's with the same tile sizes and options.
+ */
+size_t trsyl_adjoint_batched_workspace_size(int32_t count, const int64_t *m, const int64_t *n,
+                                            const int32_t *tiles, const trsyl_opts *opts);
+int trsyl_robust_adjoint_batched(int32_t count, const int64_t *m, const int64_t *n,
+                                 const double *const *A, const int64_t *lda, const double *const *B,
+                                 const int64_t *ldb, double *const *W, const int64_t *ldw,
+                                 const int32_t *tiles, int64_t *scale_log2, double *scale,
+                                 int32_t *info, const trsyl_opts *opts, void *workspace,
+                                 size_t ws_bytes, trsyl_stream_t stream);
+
+/*
  * Gradient products for L = <W, Y> with Y the scaled forward output (A Y + Y B = alpha_Y C,
  * alpha_Y = 2^-eY held fixed), given the adjoint output G with A^T G + G B^T = 2^-eG W:
  * with Gt = 2^eG G (the unscaled adjoint solution),

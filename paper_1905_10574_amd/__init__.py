@@ -72,6 +72,11 @@ def lib() -> ctypes.CDLL:
         L.trsyl_robust_batched.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                            ctypes.POINTER(Opts), _P, ctypes.c_size_t, _P]
         L.trsyl_robust_batched.restype = ctypes.c_int
+        L.trsyl_adjoint_batched_workspace_size.argtypes = [ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts)]
+        L.trsyl_adjoint_batched_workspace_size.restype = ctypes.c_size_t
+        L.trsyl_robust_adjoint_batched.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                                   _P, ctypes.POINTER(Opts), _P, ctypes.c_size_t, _P]
+        L.trsyl_robust_adjoint_batched.restype = ctypes.c_int
         L.trsyl_debug_protect_update.argtypes = [ctypes.c_int32, _P, _P, _P]
         L.trsyl_debug_protect_update.restype = ctypes.c_int
         L.trsyl_debug_protect_division.argtypes = [ctypes.c_int32, _P, _P, _P]
@@ -297,10 +302,7 @@ def trsyl(A, B, C, tile=None):
     return TrsylFunction.apply(A, B, C, tile)
 
 
-def solve_batched_async(As, Bs, Cs, tiles=None, opts: Opts | None = None):
-    """Enqueue one batched robust solve of len(As) independent problems on the current stream.
-    tiles: None (opts' tile for all), "auto" (the autotuner's table), or a list of (tile_m, tile_n).
-    Returns (Ys, e, info): Ys the column-major storages (Y_i = Ys[i].t()), e / info device tensors."""
+def _batched_async(As, Bs, Cs, tiles, opts, adjoint):
     opts = opts or make_opts()
     count = len(As)
     Acs = [colmajor(A) for A in As]
@@ -324,17 +326,40 @@ def solve_batched_async(As, Bs, Cs, tiles=None, opts: Opts | None = None):
     sc = torch.zeros(max(count, 1), dtype=torch.float64, device=dev)
     info = torch.zeros(max(count, 1), dtype=torch.int32, device=dev)
     L = lib()
-    need = int(L.trsyl_batched_workspace_size(count, m_a, n_a, t_a, ctypes.byref(opts)))
+    size_fn = L.trsyl_adjoint_batched_workspace_size if adjoint else L.trsyl_batched_workspace_size
+    entry = L.trsyl_robust_adjoint_batched if adjoint else L.trsyl_robust_batched
+    need = int(size_fn(count, m_a, n_a, t_a, ctypes.byref(opts)))
     if need == 0 and count > 0:
-        raise RuntimeError("trsyl_batched_workspace_size rejected the arguments")
+        raise RuntimeError("the batched workspace query rejected the arguments")
     ws_keep, ws_ptr = _aligned_workspace(max(need, 256), dev)
-    rc = L.trsyl_robust_batched(count, m_a, n_a, A_p, lda, B_p, ldb, C_p, ldc, t_a, e.data_ptr(),
-                                sc.data_ptr(), info.data_ptr(), ctypes.byref(opts), ws_ptr, need,
-                                _stream(dev))
+    rc = entry(count, m_a, n_a, A_p, lda, B_p, ldb, C_p, ldc, t_a, e.data_ptr(), sc.data_ptr(),
+               info.data_ptr(), ctypes.byref(opts), ws_ptr, need, _stream(dev))
     if rc != 0:
-        raise RuntimeError(f"trsyl_robust_batched rejected its arguments: {rc}")
-    solve_batched_async._keep = (Acs, Bcs, ws_keep, m_a, n_a, A_p, B_p, C_p, t_a)
+        raise RuntimeError(f"the batched solve rejected its arguments: {rc}")
+    _batched_async._keep = (Acs, Bcs, ws_keep, m_a, n_a, A_p, B_p, C_p, t_a)
     return Ycs, e, info
+
+
+def solve_batched_async(As, Bs, Cs, tiles=None, opts: Opts | None = None):
+    """Enqueue one batched robust solve of len(As) independent problems on the current stream.
+    tiles: None (opts' tile for all), "auto" (the autotuner's table), or a list of (tile_m, tile_n).
+    Returns (Ys, e, info): Ys the column-major storages (Y_i = Ys[i].t()), e / info device tensors."""
+    return _batched_async(As, Bs, Cs, tiles, opts, False)
+
+
+def adjoint_batched_async(As, Bs, Ws, tiles=None, opts: Opts | None = None):
+    """Enqueue one batched adjoint solve A_i^T G_i + G_i B_i^T = 2^-e_i W_i; returns (Gs, e, info)
+    as solve_batched_async does."""
+    return _batched_async(As, Bs, Ws, tiles, opts, True)
+
+
+def adjoint_batched(As, Bs, Ws, tiles=None, **kw):
+    """Batched adjoint solve; returns a list of (G, eG, info)."""
+    Gcs, e, info = adjoint_batched_async(As, Bs, Ws, tiles, make_opts(**kw))
+    if Gcs:
+        torch.cuda.synchronize(Gcs[0].device)
+    es, infos = e.cpu().tolist(), info.cpu().tolist()
+    return [(G.t(), int(es[i]), int(infos[i])) for i, G in enumerate(Gcs)]
 
 
 def solve_batched(As, Bs, Cs, tiles=None, **kw):

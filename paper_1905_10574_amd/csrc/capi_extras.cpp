@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/trsyl.h"
 #include "extras.hpp"
@@ -69,6 +70,89 @@ int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, con
                                 scale_log2, scale, info, opts, workspace, fw, stream_);
     if (rc != 0) return rc == -100 ? -100 : -12;
     if (m > 0 && n > 0 && launch_flip(W, ldw, mi, ni, stream) != hipSuccess) return -100;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched adjoint: every problem reversed as in trsyl_robust_adjoint, then one batched forward
+// solve.  Workspace: the batched forward workspace, then Ah_p (m_p x m_p) and Bh_p (n_p x n_p)
+// for every problem.
+// ---------------------------------------------------------------------------------------------
+namespace {
+size_t adjoint_batched_extra(int32_t count, const int64_t *m, const int64_t *n, std::vector<size_t> *offs)
+{
+    size_t o = 0;
+    for (int p = 0; p < count; ++p) {
+        if (offs) offs->push_back(o);
+        o = align_up(o + 8 * (size_t)std::max<int64_t>(m[p], 1) * std::max<int64_t>(m[p], 1));
+        if (offs) offs->push_back(o);
+        o = align_up(o + 8 * (size_t)std::max<int64_t>(n[p], 1) * std::max<int64_t>(n[p], 1));
+    }
+    return o;
+}
+}  // namespace
+
+size_t trsyl_adjoint_batched_workspace_size(int32_t count, const int64_t *m, const int64_t *n,
+                                            const int32_t *tiles, const trsyl_opts *opts)
+{
+    if (count < 0 || (count > 0 && (!m || !n))) return 0;
+    for (int p = 0; p < count; ++p)
+        if (m[p] < 0 || n[p] < 0) return 0;
+    const size_t fw = trsyl_batched_workspace_size(count, m, n, tiles, opts);
+    if (count > 0 && fw == 0) return 0;
+    return align_up(fw) + adjoint_batched_extra(count, m, n, nullptr);
+}
+
+int trsyl_robust_adjoint_batched(int32_t count, const int64_t *m, const int64_t *n, const double *const *A,
+                                 const int64_t *lda, const double *const *B, const int64_t *ldb,
+                                 double *const *W, const int64_t *ldw, const int32_t *tiles,
+                                 int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
+                                 void *workspace, size_t ws_bytes, trsyl_stream_t stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (count < 0) return -1;
+    if (count == 0) return 0;
+    if (!m || !n) return -2;
+    if (!A || !lda) return -4;
+    if (!B || !ldb) return -6;
+    if (!W || !ldw) return -8;
+    for (int p = 0; p < count; ++p) {
+        if (m[p] < 0 || n[p] < 0 || m[p] > (int64_t)INT32_MAX / 2 || n[p] > (int64_t)INT32_MAX / 2) return -2;
+        if (m[p] > 0 && bad_ptr(A[p])) return -4;
+        if (lda[p] < std::max<int64_t>(1, m[p])) return -5;
+        if (n[p] > 0 && bad_ptr(B[p])) return -6;
+        if (ldb[p] < std::max<int64_t>(1, n[p])) return -7;
+        if (m[p] > 0 && n[p] > 0 && bad_ptr(W[p])) return -8;
+        if (ldw[p] < std::max<int64_t>(1, m[p])) return -9;
+    }
+    const size_t fw = trsyl_batched_workspace_size(count, m, n, tiles, opts);
+    if (fw == 0) return -14;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -15;
+    if (ws_bytes < trsyl_adjoint_batched_workspace_size(count, m, n, tiles, opts)) return -16;
+    char *ws = (char *)workspace;
+    std::vector<size_t> offs;
+    adjoint_batched_extra(count, m, n, &offs);
+    std::vector<const double *> Ah(count), Bh(count);
+    std::vector<int64_t> ldah(count), ldbh(count);
+    for (int p = 0; p < count; ++p) {
+        double *ah = (double *)(ws + align_up(fw) + offs[2 * p]);
+        double *bh = (double *)(ws + align_up(fw) + offs[2 * p + 1]);
+        Ah[p] = ah;
+        Bh[p] = bh;
+        ldah[p] = std::max<int64_t>(1, m[p]);
+        ldbh[p] = std::max<int64_t>(1, n[p]);
+        if (m[p] > 0 && n[p] > 0) {
+            if (launch_flip_transpose(A[p], lda[p], (int)m[p], ah, stream) != hipSuccess) return -100;
+            if (launch_flip_transpose(B[p], ldb[p], (int)n[p], bh, stream) != hipSuccess) return -100;
+            if (launch_flip(W[p], ldw[p], (int)m[p], (int)n[p], stream) != hipSuccess) return -100;
+        }
+    }
+    const int rc = trsyl_robust_batched(count, m, n, Ah.data(), ldah.data(), Bh.data(), ldbh.data(), W, ldw,
+                                        tiles, scale_log2, scale, info, opts, workspace, fw, stream_);
+    if (rc != 0) return rc;
+    for (int p = 0; p < count; ++p)
+        if (m[p] > 0 && n[p] > 0 && launch_flip(W[p], ldw[p], (int)m[p], (int)n[p], stream) != hipSuccess)
+            return -100;
     return 0;
 }
 
