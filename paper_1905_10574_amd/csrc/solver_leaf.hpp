@@ -11,11 +11,14 @@
 // zeros outside the block, so its register keeps only the (tiny) residual of its block.
 //
 // Every division of the step loop is taken out of it: 1x1 blocks keep the reciprocal of
-// a_rr + b_cc, and the Gaussian eliminations with complete pivoting of the 2- and 4-unknown
-// block systems (Sec. 2.1) are factored once per leaf, one block per lane, into LDS.  At a step
-// that solves a multi-entry block, each lane of the block gathers the block's right-hand sides
-// by cross-lane permutes and applies the stored factors itself, so a step needs one LDS round
-// trip (publish the solved values, then read the sources).
+// a_rr + b_cc, and the 2- and 4-unknown block systems (Sec. 2.1) are factored once per leaf by
+// Gaussian elimination with complete pivoting, one block per lane, and the factors applied to
+// the unit vectors, which stores each block's inverse in LDS.  Every lane keeps, in registers,
+// the row of that inverse belonging to the next entry it finalises, loaded at least two steps
+// ahead; at a step that solves a multi-entry block, each lane of the block gathers the block's
+// right-hand sides by cross-lane permutes and takes its unknown as one short dot product, so a
+// step needs the permutes and one LDS round trip (publish the solved values, read the sources).
+// A block beyond the stored slots is factored and solved at its step instead.
 #pragma once
 #include "device_common.hpp"
 #include "plan.hpp"
@@ -42,11 +45,9 @@ struct LeafLds {
     uint32_t tcY[kTab];      //   the same rows as offsets inside a column of R (r * 8)
     uint32_t trY[kTab];      // k-th block column from the left, offsets into R columns (c * kSlab)
     uint32_t trB[kTab];      //   the same columns as offsets inside a column of Bl (c * 8)
-    double f2[kF2Slots][4];
-    uint32_t s2[kF2Slots];
-    double f4[kF4Slots][16];
-    uint32_t p4[kF4Slots];
-    uint8_t slot[16 * 16];  // factorisation slot of the block with top-left entry (r, c)
+    double f2[kF2Slots][4];      // inverses of 2-unknown blocks, row k at [2k], [2k + 1]
+    double f4[kF4Slots][16];     // inverses of 4-unknown blocks in position order, row t at [4t ..]
+    uint8_t slot[16 * 16];       // inverse slot of the block with top-left entry (r, c)
 };
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -307,11 +308,14 @@ __device__ __forceinline__ int leaf_setup(LeafLds &L, const LeafMasks &M, double
             good = factor2_cp(arr + bcc, L.Bl[cb * kLd + cb + 1], L.Bl[(cb + 1) * kLd + cb],
                               arr + L.Bl[(cb + 1) * kLd + cb + 1], smin, F);
         if (!good) ok = 0;
-        L.f2[lane][0] = F.l;
-        L.f2[lane][1] = F.p1;
-        L.f2[lane][2] = F.rp0;
-        L.f2[lane][3] = F.ru11;
-        L.s2[lane] = (uint32_t)F.sw;
+        // the inverse's columns: the factors applied to the unit vectors
+        double x00 = 1.0, x10 = 0.0, x01 = 0.0, x11 = 1.0;
+        apply2(F, x00, x10);
+        apply2(F, x01, x11);
+        L.f2[lane][0] = x00;
+        L.f2[lane][1] = x01;
+        L.f2[lane][2] = x10;
+        L.f2[lane][3] = x11;
         L.slot[ra * 16 + cb] = (uint8_t)lane;
     }
     if (lane < A2 * B2 && lane < kF4Slots) {
@@ -325,9 +329,17 @@ __device__ __forceinline__ int leaf_setup(LeafLds &L, const LeafMasks &M, double
             b[t] = L.Bl[(cb + pp) * kLd + cb + p];
         }
         if (!factor4_cp(a, b, smin, f, pm)) ok = 0;
+        // column j of the inverse: the right-hand side e_j in the factorisation's row order,
+        // the unknowns come back in its column order
 #pragma unroll
-        for (int t = 0; t < 16; ++t) L.f4[lane][t] = f[t];
-        L.p4[lane] = pm;
+        for (int j = 0; j < 4; ++j) {
+            double v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = ((pm >> (2 * t)) & 3u) == (uint32_t)j ? 1.0 : 0.0;
+            apply4(f, v);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) L.f4[lane][4 * ((pm >> (8 + 2 * t)) & 3u) + j] = v[t];
+        }
         L.slot[ra * 16 + cb] = (uint8_t)lane;
     }
     wave_sync_lds();
@@ -338,10 +350,11 @@ __device__ __forceinline__ int leaf_setup(LeafLds &L, const LeafMasks &M, double
 // The step loop.  Returns 0 in a lane where a pivot fell below smin or a value it produced
 // exceeded Tc (the first non-finite value is an infinity, which the running maximum keeps).
 // With vmax_out, the lane's largest magnitude is stored there instead and only the pivots
-// decide the return value.
+// decide the return value.  MULTI = false is the loop of a leaf made of 1x1 blocks only.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc,
-                                          const LeafMasks &M, double *vmax_out = nullptr)
+template <bool MULTI>
+__device__ __forceinline__ int leaf_solve_t(LeafLds &L, int nr, int nc, double smin, double Tc,
+                                            const LeafMasks &M, double *vmax_out)
 {
     constexpr int E = 4;
     const int lane = threadIdx.x & 63;
@@ -386,6 +399,38 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
             rdd[i] = 1.0 / dd;
         }
     }
+    // cn: the row of the block inverse of the entry this lane finalises next, over the block's
+    // positions p + 2 pp (a 1x1 block: its reciprocal in cn[0]); a block without a stored inverse
+    // leaves zeros and is solved from its factorisation at its step
+    double cn[4] = {0.0, 0.0, 0.0, 0.0};
+    auto fetch = [&](uint32_t inf, double rd) __attribute__((always_inline)) {
+        const uint32_t kind = inf & 3u, pos = (inf >> 2) & 3u, sl = (inf >> 4) & 255u;
+        if (kind == 0u) {
+            cn[0] = rd; cn[1] = 0.0; cn[2] = 0.0; cn[3] = 0.0;
+        } else if (sl == kNoSlot) {
+            cn[0] = 0.0; cn[1] = 0.0; cn[2] = 0.0; cn[3] = 0.0;
+        } else if (kind == 3u) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) cn[t] = L.f4[sl][4 * pos + t];
+        } else {
+            const uint32_t k = kind == 1u ? pos : pos >> 1;
+            const double x0 = L.f2[sl][2 * k], x1 = L.f2[sl][2 * k + 1];
+            cn[0] = x0;
+            cn[1] = kind == 1u ? x1 : 0.0;
+            cn[2] = kind == 1u ? 0.0 : x1;
+            cn[3] = 0.0;
+        }
+    };
+    if constexpr (MULTI) {
+        // entries finalise from the last valid one (largest row) upwards
+        uint32_t finf = 0u;
+        double frd = 1.0;
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+            if (fin[i] >= 0) { finf = info[i]; frd = rdd[i]; any = true; }
+        if (any) fetch(finf, frd);
+    }
     const char *Rb = (const char *)L.R, *Ab = (const char *)L.Al, *Bb = (const char *)L.Bl;
     const char *Rc = Rb + c * kSlab, *Bc = Bb + c * kSlab;
     // Software pipeline: the source tables of step s + 2 and the coefficients of step s + 1 are
@@ -418,32 +463,34 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
         // the entry this lane finalises at step s, if any (at most one: its rows lie in distinct
         // block rows)
         double accf = 0.0, rdf = 1.0;
-        int rf = -1;
+        int rf = -1, fi = -1;
         uint32_t inf = 0u;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            if (fin[i] == s) { accf = acc[i]; rdf = rdd[i]; rf = q + 4 * i; inf = info[i]; }
+            if (fin[i] == s) {
+                accf = acc[i]; rf = q + 4 * i; fi = i;
+                if constexpr (MULTI) inf = info[i];
+                else rdf = rdd[i];
+            }
         }
-        double yf = accf * rdf;
-        if ((msteps >> s) & 1u) {
+        double yf;
+        if (MULTI && ((msteps >> s) & 1u)) {
             const uint32_t kind = inf & 3u, pos = (inf >> 2) & 3u, sl = (inf >> 4) & 255u;
             const int bl = (int)(inf >> 12);
-            const uint32_t pm = (kind == 3u && sl != kNoSlot) ? L.p4[sl] : 0xE4E4u;
-            // the block's right-hand sides, in the factorisation's row order
+            // the block's right-hand sides in position order p + 2 pp (entry (rb0 + p, cb0 + pp)
+            // sits in lane cb0 + pp + 16 ((rb0 + p) & 3)); positions outside the block read as 0
             double g[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int e = (int)((pm >> (2 * t)) & 3u);
-                g[t] = __shfl(accf, (bl + 16 * (e & 1) + (e >> 1)) & 63, 64);
-            }
-            if (rf >= 0 && (kind == 1u || kind == 2u)) {
+            for (int t = 0; t < 4; ++t) g[t] = __shfl(accf, (bl + 16 * (t & 1) + (t >> 1)) & 63, 64);
+            const double g1 = (kind & 1u) ? g[1] : 0.0, g2 = (kind & 2u) ? g[2] : 0.0;
+            const double g3 = kind == 3u ? g[3] : 0.0;
+            yf = fma(cn[3], g3, fma(cn[2], g2, fma(cn[1], g1, cn[0] * g[0])));
+            if (rf >= 0 && kind != 0u && sl == kNoSlot) {
+                // no stored inverse: factor the block here
                 const int ra = rf - (int)(pos & 1u), cb = c - (int)(pos >> 1);
-                Factor2 F;
-                if (sl != kNoSlot) {
-                    F.l = L.f2[sl][0]; F.p1 = L.f2[sl][1]; F.rp0 = L.f2[sl][2]; F.ru11 = L.f2[sl][3];
-                    F.sw = (int)L.s2[sl];
-                } else {
+                if (kind != 3u) {
                     const double arr = L.Al[ra * kLd + ra], bb = L.Bl[cb * kLd + cb];
+                    Factor2 F;
                     bool good;
                     if (kind == 1u)
                         good = factor2_cp(arr + bb, L.Al[(ra + 1) * kLd + ra], L.Al[ra * kLd + ra + 1],
@@ -452,19 +499,10 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
                         good = factor2_cp(arr + bb, L.Bl[cb * kLd + cb + 1], L.Bl[(cb + 1) * kLd + cb],
                                           arr + L.Bl[(cb + 1) * kLd + cb + 1], smin, F);
                     if (!good) ok = 0;
-                }
-                double v0 = g[0], v1 = kind == 1u ? g[1] : g[2];
-                apply2(F, v0, v1);
-                yf = pos == 0u ? v0 : v1;
-            } else if (rf >= 0 && kind == 3u) {
-                if (sl != kNoSlot) {
-                    double v[4] = {g[0], g[1], g[2], g[3]};
-                    apply4(L.f4[sl], v);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (((pm >> (8 + 2 * t)) & 3u) == pos) yf = v[t];
+                    double v0 = g[0], v1 = kind == 1u ? g[1] : g[2];
+                    apply2(F, v0, v1);
+                    yf = pos == 0u ? v0 : v1;
                 } else {
-                    const int ra = rf - (int)(pos & 1u), cb = c - (int)(pos >> 1);
                     double a[4], b[4], f[16], w[4];
                     uint32_t pm2;
 #pragma unroll
@@ -485,6 +523,8 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
                         if (((pm2 >> (8 + 2 * t)) & 3u) == pos) yf = w[t];
                 }
             }
+        } else {
+            yf = accf * (MULTI ? cn[0] : rdf);       // only 1x1 blocks finalise at this step
         }
         if (rf >= 0) {
             vmax = fmax(vmax, fabs(yf));
@@ -498,6 +538,15 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
         for (int i = 0; i < E; ++i) {
             z0[i] = lds_at(Rb, (Tc_.tz[i] & 0xffffu) + 8 * (q + 4 * i));
             z1[i] = lds_at(Rb, (Tc_.tz[i] >> 16) + 8 * (q + 4 * i));
+        }
+        if constexpr (MULTI) {
+            // the inverse row of the entry above the one just finalised (used two or more steps on)
+            uint32_t ninf = 0u;
+            double nrd = 1.0;
+#pragma unroll
+            for (int i = 1; i < E; ++i)
+                if (fi == i) { ninf = info[i - 1]; nrd = rdd[i - 1]; }
+            if (fi > 0) fetch(ninf, nrd);
         }
         coefs(Tn, Cn);
         tables(s + 2, Tc_);
@@ -527,6 +576,12 @@ __device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smi
     if (vmax_out) *vmax_out = vmax;
     else if (!(vmax <= Tc)) ok = 0;
     return ok;
+}
+__device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc,
+                                          const LeafMasks &M, double *vmax_out = nullptr)
+{
+    if (M.m2 | M.n2) return leaf_solve_t<true>(L, nr, nc, smin, Tc, M, vmax_out);
+    return leaf_solve_t<false>(L, nr, nc, smin, Tc, M, vmax_out);
 }
 
 }  // namespace trsyl
