@@ -81,7 +81,8 @@ typedef struct trsyl_opts {
                              RobustUpdate, Algorithm 3), [2] tile solves whose unscaled
                              certificate failed, so that the leaf-tiled robust solve ran,
                              [3] zero.
-                             trsyl_robust and trsyl_robust_adjoint fill it (for
+                             trsyl_robust, trsyl_robust_adjoint and trsyl_robust_general
+                             fill it (for
                              TRSYL_FP32_REFINE: the counts of the first, FP32-update solve);
                              trsyl_robust_batched ignores it */
 } trsyl_opts;
@@ -122,6 +123,24 @@ int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, con
                          int64_t ldb, double *W, int64_t ldw, int64_t *scale_log2, double *scale,
                          int32_t *info, const trsyl_opts *opts, void *workspace, size_t ws_bytes,
                          trsyl_stream_t stream);
+
+/*
+ * General form op(A) Y + isgn Y op(B) = alpha C (the triangular Sylvester equation of Sec. 1 with
+ * either coefficient transposed and either sign; with B = A and tranb = 'T' it is the Lyapunov
+ * equation A Y + Y A^T = alpha C, which Sec. 1 names as a special case).
+ *   trana, tranb    'N': op(X) = X;  'T' (or 'C'): op(X) = X^T
+ *   isgn            +1 or -1
+ *   other arguments as in trsyl_robust (argument i of this list is reported as -i); A and B are
+ *   read only; workspace >= trsyl_general_workspace_size(m, n, opts).
+ * A transposed coefficient is mapped onto the forward problem by order reversal as in
+ * trsyl_robust_adjoint (P A^T P upper quasi-triangular, the rows of C reversed; Q B^T Q, the
+ * columns of C reversed); isgn = -1 solves with -op(B).  'N', 'N', +1 is trsyl_robust.
+ */
+size_t trsyl_general_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts);
+int trsyl_robust_general(char trana, char tranb, int32_t isgn, int64_t m, int64_t n, const double *A,
+                         int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
+                         int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
+                         void *workspace, size_t ws_bytes, trsyl_stream_t stream);
 
 /*
  * Batched adjoint solve: `count` independent problems A_i^T G_i + G_i B_i^T = alpha_i W_i (the

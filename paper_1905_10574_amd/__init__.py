@@ -59,6 +59,10 @@ def lib() -> ctypes.CDLL:
         L.trsyl_adjoint_workspace_size.restype = ctypes.c_size_t
         L.trsyl_robust_adjoint.argtypes = L.trsyl_robust.argtypes
         L.trsyl_robust_adjoint.restype = ctypes.c_int
+        L.trsyl_general_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(Opts)]
+        L.trsyl_general_workspace_size.restype = ctypes.c_size_t
+        L.trsyl_robust_general.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int32] + list(L.trsyl_robust.argtypes)
+        L.trsyl_robust_general.restype = ctypes.c_int
         L.trsyl_grad.argtypes = [_I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _I64, _P,
                                  _P, _I64, _P, _I64, _P, _I64, _P]
         L.trsyl_grad.restype = ctypes.c_int
@@ -222,6 +226,42 @@ def adjoint(A, B, W, **kw):
     Gc, e, info = adjoint_async(A, B, W, make_opts(**kw))
     torch.cuda.synchronize(Gc.device)
     return Gc.t(), int(e.item()), int(info.item())
+
+
+def general_async(A, B, C, trana="N", tranb="N", isgn=1, opts: Opts | None = None):
+    """Enqueue op(A) Y + isgn Y op(B) = alpha C (op(X) = X for "N", X^T for "T").  Returns
+    (Ys, e, info) device tensors with Ys the column-major storage of Y (Y = Ys.t())."""
+    opts = opts or make_opts()
+    Ac = colmajor(A)
+    dev = Ac.device
+    Bc = colmajor(B, dev)
+    Yc = colmajor(C, dev)
+    m, n = Yc.shape[1], Yc.shape[0]
+    e = torch.zeros(1, dtype=torch.int64, device=dev)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = int(lib().trsyl_general_workspace_size(m, n, ctypes.byref(opts)))
+    ws_keep, ws_ptr = _aligned_workspace(need, dev)
+    rc = lib().trsyl_robust_general(trana.encode(), tranb.encode(), int(isgn), m, n, Ac.data_ptr(),
+                                    max(1, m), Bc.data_ptr(), max(1, n), Yc.data_ptr(), max(1, m),
+                                    e.data_ptr(), sc.data_ptr(), info.data_ptr(), ctypes.byref(opts),
+                                    ws_ptr, need, _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_robust_general rejected its arguments: {rc}")
+    general_async._keep = (Ac, Bc, ws_keep)
+    return Yc, e, info
+
+
+def solve_general(A, B, C, trana="N", tranb="N", isgn=1, **kw):
+    """General-form solve; returns (Y, e, info) with op(A) Y + isgn Y op(B) = 2^-e C."""
+    Yc, e, info = general_async(A, B, C, trana, tranb, isgn, make_opts(**kw))
+    torch.cuda.synchronize(Yc.device)
+    return Yc.t(), int(e.item()), int(info.item())
+
+
+def lyapunov(A, C, **kw):
+    """Lyapunov solve A Y + Y A^T = 2^-e C (A upper quasi-triangular); returns (Y, e, info)."""
+    return solve_general(A, A, C, "N", "T", 1, **kw)
 
 
 def grad(A, B, Y, eY, G, eG):

@@ -1,5 +1,6 @@
 // Entry points of include/trsyl.h beside the forward, precision-form and batched solves (those
-// are in capi.cpp): the adjoint solve, the gradient products and the eq. (9) residual.
+// are in capi.cpp): the adjoint and general-form solves, the gradient products and the eq. (9)
+// residual.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,6 +71,75 @@ int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, con
                                 scale_log2, scale, info, opts, workspace, fw, stream_);
     if (rc != 0) return rc == -100 ? -100 : -12;
     if (m > 0 && n > 0 && launch_flip(W, ldw, mi, ni, stream) != hipSuccess) return -100;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// General form op(A) Y + isgn Y op(B) = alpha C.  A transposed A is reversed as in the adjoint
+// (Ah = P A^T P, rows of C reversed), a transposed B likewise (Bh = Q B^T Q, columns of C
+// reversed), and isgn = -1 negates the B operand; the forward driver solves
+// Ah Yh + Yh (isgn Bh) = alpha Ch and the reversals are undone on the result.  A and B are read
+// in place when they need neither.  Workspace: the forward workspace, then Ah (m x m), Bh (n x n).
+// ---------------------------------------------------------------------------------------------
+static int trans_code(char t)
+{
+    if (t == 'N' || t == 'n') return 0;
+    if (t == 'T' || t == 't' || t == 'C' || t == 'c') return 1;
+    return -1;
+}
+
+size_t trsyl_general_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts)
+{
+    return trsyl_adjoint_workspace_size(m, n, opts);
+}
+
+int trsyl_robust_general(char trana, char tranb, int32_t isgn, int64_t m, int64_t n, const double *A,
+                         int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
+                         int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
+                         void *workspace, size_t ws_bytes, trsyl_stream_t stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    const int ta = trans_code(trana), tb = trans_code(tranb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (isgn != 1 && isgn != -1) return -3;
+    if (m < 0) return -4;
+    if (n < 0) return -5;
+    if (m > 0 && bad_ptr(A)) return -6;
+    if (lda < std::max<int64_t>(1, m)) return -7;
+    if (n > 0 && bad_ptr(B)) return -8;
+    if (ldb < std::max<int64_t>(1, n)) return -9;
+    if (m > 0 && n > 0 && bad_ptr(C)) return -10;
+    if (ldc < std::max<int64_t>(1, m)) return -11;
+    if (bad_ptr(scale_log2)) return -12;
+    if (bad_ptr(info)) return -14;
+    const size_t fw = trsyl_workspace_size(m, n, opts);
+    if (fw == 0) return -15;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -16;
+    if (ws_bytes < trsyl_general_workspace_size(m, n, opts)) return -17;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -4;
+    char *ws = (char *)workspace;
+    double *Ah = (double *)(ws + align_up(fw));
+    double *Bh = (double *)(ws + align_up(fw) + align_up(8 * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(m, 1)));
+    const int mi = (int)m, ni = (int)n;
+    const bool work = m > 0 && n > 0;
+    const double *Au = A, *Bu = B;
+    int64_t ldau = lda, ldbu = ldb;
+    if (work && ta) {
+        if (launch_quasi_copy(A, lda, mi, true, 1.0, Ah, stream) != hipSuccess) return -100;
+        Au = Ah;
+        ldau = m;
+    }
+    if (work && (tb || isgn < 0)) {
+        if (launch_quasi_copy(B, ldb, ni, tb != 0, (double)isgn, Bh, stream) != hipSuccess) return -100;
+        Bu = Bh;
+        ldbu = n;
+    }
+    if (work && launch_flip_axes(C, ldc, mi, ni, ta != 0, tb != 0, stream) != hipSuccess) return -100;
+    const int rc = trsyl_robust(m, n, Au, ldau, Bu, ldbu, C, ldc, scale_log2, scale, info, opts,
+                                workspace, fw, stream_);
+    if (rc != 0) return rc == -100 ? -100 : -15;
+    if (work && launch_flip_axes(C, ldc, mi, ni, ta != 0, tb != 0, stream) != hipSuccess) return -100;
     return 0;
 }
 

@@ -20,29 +20,39 @@ constexpr int kGK = 16;       // k per LDS stage
 constexpr int kGS = kGT + 2;  // padded LDS row
 
 // ---------------------------------------------------------------------------------------------
-// Ah(p, q) = A(n-1-q, n-1-p) on and above the first subdiagonal, zero below.
+// D(p, q) = sign * T(p, q), or sign * T(n-1-q, n-1-p) with flip (the order-reversed transpose
+// P T^T P, again upper quasi-triangular), on and above the first subdiagonal; zero below.
 // ---------------------------------------------------------------------------------------------
-__global__ void k_flip_transpose(const double *A, int64_t lda, int n, double *Ah)
+__global__ void k_quasi_copy(const double *T, int64_t ldt, int n, int flip, double sign, double *D)
 {
     const int64_t tot = (int64_t)n * n;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int p = (int)(t % n), q = (int)(t / n);
         double v = 0.0;
-        if (p <= q + 1) v = ldg(A + (int64_t)(n - 1 - p) * lda + (n - 1 - q));
-        stg(Ah + (int64_t)q * n + p, v);
+        if (p <= q + 1) {
+            const double x = flip ? ldg(T + (int64_t)(n - 1 - p) * ldt + (n - 1 - q))
+                                  : ldg(T + (int64_t)q * ldt + p);
+            v = sign * x;
+        }
+        stg(D + (int64_t)q * n + p, v);
     }
 }
 
-// W(i, j) <-> W(m-1-i, n-1-j), in place.
-__global__ void k_flip(double *W, int64_t ldw, int m, int n)
+// In place: W(i, j) <-> W(m-1-i, n-1-j) (rows and cols), W(m-1-i, j) (rows only) or
+// W(i, n-1-j) (cols only); each pair is swapped by one thread.
+__global__ void k_flip_axes(double *W, int64_t ldw, int m, int n, int rows, int cols)
 {
-    const int64_t tot = (int64_t)m * n, half = tot / 2;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < half;
+    const int mh = m / 2, nh = n / 2;
+    const int64_t pairs = rows && cols ? (int64_t)m * n / 2 : rows ? (int64_t)mh * n : (int64_t)m * nh;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < pairs;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % m), j = (int)(e / m);
+        int i, j, i2, j2;
+        if (rows && cols) { i = (int)(e % m); j = (int)(e / m); i2 = m - 1 - i; j2 = n - 1 - j; }
+        else if (rows) { i = (int)(e % mh); j = (int)(e / mh); i2 = m - 1 - i; j2 = j; }
+        else { i = (int)(e % m); j = (int)(e / m); i2 = i; j2 = n - 1 - j; }
         double *p = W + (int64_t)j * ldw + i;
-        double *q = W + (int64_t)(n - 1 - j) * ldw + (m - 1 - i);
+        double *q = W + (int64_t)j2 * ldw + i2;
         const double a = ldg(p), b = ldg(q);
         stg(p, b);
         stg(q, a);
@@ -353,18 +363,31 @@ static int grid_for(int64_t work, int per = 256)
     return (int)g;
 }
 
-hipError_t launch_flip_transpose(const double *A, int64_t lda, int n, double *Ah, hipStream_t s)
+hipError_t launch_quasi_copy(const double *T, int64_t ldt, int n, bool flip, double sign, double *D,
+                             hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flip_transpose, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, A, lda, n, Ah);
+    hipLaunchKernelGGL(k_quasi_copy, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, T, ldt, n,
+                       flip ? 1 : 0, sign, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_transpose(const double *A, int64_t lda, int n, double *Ah, hipStream_t s)
+{
+    return launch_quasi_copy(A, lda, n, true, 1.0, Ah, s);
+}
+
+hipError_t launch_flip_axes(double *W, int64_t ldw, int m, int n, bool rows, bool cols, hipStream_t s)
+{
+    if (m <= 0 || n <= 0 || (!rows && !cols)) return hipSuccess;
+    hipLaunchKernelGGL(k_flip_axes, dim3(grid_for((int64_t)m * n / 2 + 1)), dim3(256), 0, s, W, ldw, m,
+                       n, rows ? 1 : 0, cols ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_flip(double *W, int64_t ldw, int m, int n, hipStream_t s)
 {
-    if (m <= 0 || n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flip, dim3(grid_for((int64_t)m * n / 2 + 1)), dim3(256), 0, s, W, ldw, m, n);
-    return hipGetLastError();
+    return launch_flip_axes(W, ldw, m, n, true, true, s);
 }
 
 hipError_t launch_gemm(const GemmDesc &g, hipStream_t s)

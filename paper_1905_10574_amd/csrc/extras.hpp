@@ -40,7 +40,10 @@ struct GemmDesc {
     int64_t ldpat;
 };
 
+hipError_t launch_quasi_copy(const double *T, int64_t ldt, int n, bool flip, double sign, double *D,
+                             hipStream_t s);
 hipError_t launch_flip_transpose(const double *A, int64_t lda, int n, double *Ah, hipStream_t s);
+hipError_t launch_flip_axes(double *W, int64_t ldw, int m, int n, bool rows, bool cols, hipStream_t s);
 hipError_t launch_flip(double *W, int64_t ldw, int m, int n, hipStream_t s);
 hipError_t launch_gemm(const GemmDesc &g, hipStream_t s);
 hipError_t launch_scale_copy(const double *G, int64_t ldg_, int m, int n, const int64_t *eG,

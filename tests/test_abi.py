@@ -64,3 +64,29 @@ def test_argument_errors_are_reported_without_a_device(lib):
     assert lib.trsyl_robust(4, 4, dummy, 3, dummy, 4, dummy, 4, dummy, None, dummy, None, dummy, 1 << 20, None) == -4
     assert lib.trsyl_robust(4, 4, dummy, 4, dummy, 4, dummy, 4, None, None, dummy, None, dummy, 1 << 20, None) == -9
     assert lib.trsyl_robust(4, 4, dummy, 4, dummy, 4, dummy, 4, dummy, None, dummy, None, dummy, 8, None) == -14
+
+
+def test_general_form_argument_errors(lib):
+    """trsyl_robust_general reports argument i as -i on the host (LAPACK convention)."""
+    P, I64 = ctypes.c_void_p, ctypes.c_int64
+    lib.trsyl_robust_general.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int32, I64, I64, P, I64,
+                                         P, I64, P, I64, P, P, P, P, P, ctypes.c_size_t, P]
+    d = ctypes.c_void_p(256)
+
+    def call(ta=b"N", tb=b"N", sg=1, m=4, n=4, A=d, lda=4, B=d, ldb=4, C=d, ldc=4, e=d, info=d, ws=1 << 24):
+        return lib.trsyl_robust_general(ta, tb, sg, m, n, A, lda, B, ldb, C, ldc, e, None, info, None, d, ws, None)
+
+    assert call(ta=b"X") == -1
+    assert call(tb=b"Q") == -2
+    assert call(sg=0) == -3 and call(sg=2) == -3
+    assert call(m=-1) == -4
+    assert call(n=-2) == -5
+    assert call(A=None) == -6
+    assert call(lda=3) == -7
+    assert call(B=None) == -8
+    assert call(ldb=2) == -9
+    assert call(C=None) == -10
+    assert call(ldc=1) == -11
+    assert call(e=None) == -12
+    assert call(info=None) == -14
+    assert call(ws=8) == -17
