@@ -143,6 +143,28 @@ int trsyl_robust_general(char trana, char tranb, int32_t isgn, int64_t m, int64_
                          void *workspace, size_t ws_bytes, trsyl_stream_t stream);
 
 /*
+ * Bartels-Stewart solve of A X + X B = alpha C for general A, B (Sec. 1): the caller supplies
+ * real Schur forms A = U At U^T, B = V Bt V^T (U, V orthogonal; At, Bt upper quasi-triangular,
+ * e.g. from LAPACK dgees).  The library forms Ct = U^T C V, solves At Y + Y Bt = alpha Ct with
+ * trsyl_robust, and returns X = U Y V^T in C.
+ *   U, ldu / V, ldv     device, m x m / n x n, read only
+ *   At, ldat / Bt, ldbt device, m x m / n x n, read only (as A, B of trsyl_robust)
+ *   C, ldc              device, m x n; in: C, out: X
+ *   other arguments as in trsyl_robust (argument i of this list is reported as -i);
+ *   workspace >= trsyl_bartels_stewart_workspace_size(m, n, opts).
+ * The four orthogonal transforms are FP64 GEMMs that cannot overflow: C, and then Y, enters its
+ * first transform times the power of two that brings its Frobenius norm to OMEGA or below (every
+ * partial sum of a transformed entry is bounded by that norm), and both shifts are added to e,
+ * so X = 2^-e times the solution with e the total exponent.
+ */
+size_t trsyl_bartels_stewart_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts);
+int trsyl_bartels_stewart(int64_t m, int64_t n, const double *U, int64_t ldu, const double *At,
+                          int64_t ldat, const double *V, int64_t ldv, const double *Bt, int64_t ldbt,
+                          double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                          const trsyl_opts *opts, void *workspace, size_t ws_bytes,
+                          trsyl_stream_t stream);
+
+/*
  * Batched adjoint solve: `count` independent problems A_i^T G_i + G_i B_i^T = alpha_i W_i (the
  * transposed problems of Sec. 8's gradient derivation), each reversed as in trsyl_robust_adjoint
  * and all solved by one batched forward solve (trsyl_robust_batched).  Arguments as in

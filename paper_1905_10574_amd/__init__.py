@@ -63,6 +63,11 @@ def lib() -> ctypes.CDLL:
         L.trsyl_general_workspace_size.restype = ctypes.c_size_t
         L.trsyl_robust_general.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int32] + list(L.trsyl_robust.argtypes)
         L.trsyl_robust_general.restype = ctypes.c_int
+        L.trsyl_bartels_stewart_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(Opts)]
+        L.trsyl_bartels_stewart_workspace_size.restype = ctypes.c_size_t
+        L.trsyl_bartels_stewart.argtypes = [_I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64,
+                                            _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+        L.trsyl_bartels_stewart.restype = ctypes.c_int
         L.trsyl_grad.argtypes = [_I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _I64, _P,
                                  _P, _I64, _P, _I64, _P, _I64, _P]
         L.trsyl_grad.restype = ctypes.c_int
@@ -262,6 +267,30 @@ def solve_general(A, B, C, trana="N", tranb="N", isgn=1, **kw):
 def lyapunov(A, C, **kw):
     """Lyapunov solve A Y + Y A^T = 2^-e C (A upper quasi-triangular); returns (Y, e, info)."""
     return solve_general(A, A, C, "N", "T", 1, **kw)
+
+
+def bartels_stewart(U, At, V, Bt, C, **kw):
+    """A X + X B = 2^-e C from the real Schur forms A = U At U^T, B = V Bt V^T (computed by the
+    caller); returns (X, e, info)."""
+    opts = make_opts(**kw)
+    Uc = colmajor(U)
+    dev = Uc.device
+    Atc, Vc, Btc, Xc = colmajor(At, dev), colmajor(V, dev), colmajor(Bt, dev), colmajor(C, dev)
+    m, n = Xc.shape[1], Xc.shape[0]
+    e = torch.zeros(1, dtype=torch.int64, device=dev)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = int(lib().trsyl_bartels_stewart_workspace_size(m, n, ctypes.byref(opts)))
+    ws_keep, ws_ptr = _aligned_workspace(need, dev)
+    rc = lib().trsyl_bartels_stewart(m, n, Uc.data_ptr(), max(1, m), Atc.data_ptr(), max(1, m),
+                                     Vc.data_ptr(), max(1, n), Btc.data_ptr(), max(1, n), Xc.data_ptr(),
+                                     max(1, m), e.data_ptr(), sc.data_ptr(), info.data_ptr(),
+                                     ctypes.byref(opts), ws_ptr, need, _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_bartels_stewart rejected its arguments: {rc}")
+    torch.cuda.synchronize(dev)
+    del ws_keep
+    return Xc.t(), int(e.item()), int(info.item())
 
 
 def grad(A, B, Y, eY, G, eG):

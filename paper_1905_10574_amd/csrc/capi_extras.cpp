@@ -1,6 +1,6 @@
 // Entry points of include/trsyl.h beside the forward, precision-form and batched solves (those
-// are in capi.cpp): the adjoint and general-form solves, the gradient products and the eq. (9)
-// residual.
+// are in capi.cpp): the adjoint, general-form and Bartels-Stewart solves, the gradient products
+// and the eq. (9) residual.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -140,6 +140,101 @@ int trsyl_robust_general(char trana, char tranb, int32_t isgn, int64_t m, int64_
                                 workspace, fw, stream_);
     if (rc != 0) return rc == -100 ? -100 : -15;
     if (work && launch_flip_axes(C, ldc, mi, ni, ta != 0, tb != 0, stream) != hipSuccess) return -100;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bartels-Stewart (Sec. 1): A X + X B = alpha C with A = U At U^T, B = V Bt V^T in real Schur
+// form.  Ct = U^T C V (two GEMMs through a workspace panel, the second written over C), the
+// robust triangular solve At Y + Y Bt = alpha Ct in place, then X = U Y V^T (two GEMMs).  The
+// transforms cannot overflow: with orthogonal U, V every partial sum of a transformed entry is
+// bounded by the Frobenius norm of the matrix being transformed (Cauchy-Schwarz), so C and then
+// Y enter their first GEMM times the power of two that brings that norm to OMEGA or below, and
+// the two shifts are added to the scale exponent.
+// Workspace: the forward workspace, one m x n panel, the norm partials and a few scalars.
+// ---------------------------------------------------------------------------------------------
+size_t trsyl_bartels_stewart_workspace_size(int64_t m, int64_t n, const trsyl_opts *opts)
+{
+    const size_t fw = trsyl_workspace_size(m, n, opts);
+    if (fw == 0) return 0;
+    return align_up(fw) + align_up(8 * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(n, 1)) +
+           align_up(8 * (size_t)kNormParts) + kAlign;
+}
+
+// Out = Aop Bop with the B operand staged times 2^(*bexp) (bexp: device int64)
+static hipError_t plain_gemm(int M, int N, int K, const double *A, int64_t sAm, int64_t sAk,
+                             const double *B, int64_t sBk, int64_t sBn, const int64_t *bexp, double *Out,
+                             int64_t ldo, hipStream_t stream)
+{
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.sAm = sAm; g.sAk = sAk; g.triA = 0;
+    g.B = B; g.sBk = sBk; g.sBn = sBn; g.triB = 0;
+    g.Cin = nullptr; g.ldcin = 1;
+    g.Out = Out; g.ldo = ldo;
+    g.sa1 = 0; g.sb1 = bexp ? 1 : 0;
+    g.asign = 1.0; g.ae0 = 0; g.ae1 = 0; g.ae2 = 0;
+    g.csign = 0.0; g.ce0 = 0; g.ce1 = 0; g.ce2 = 0;
+    g.ep1 = bexp; g.ep2 = bexp;
+    g.mask = 0; g.pat = nullptr; g.ldpat = 1;
+    return launch_gemm(g, stream);
+}
+
+int trsyl_bartels_stewart(int64_t m, int64_t n, const double *U, int64_t ldu, const double *At,
+                          int64_t ldat, const double *V, int64_t ldv, const double *Bt, int64_t ldbt,
+                          double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                          const trsyl_opts *opts, void *workspace, size_t ws_bytes,
+                          trsyl_stream_t stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && bad_ptr(U)) return -3;
+    if (ldu < std::max<int64_t>(1, m)) return -4;
+    if (m > 0 && bad_ptr(At)) return -5;
+    if (ldat < std::max<int64_t>(1, m)) return -6;
+    if (n > 0 && bad_ptr(V)) return -7;
+    if (ldv < std::max<int64_t>(1, n)) return -8;
+    if (n > 0 && bad_ptr(Bt)) return -9;
+    if (ldbt < std::max<int64_t>(1, n)) return -10;
+    if (m > 0 && n > 0 && bad_ptr(C)) return -11;
+    if (ldc < std::max<int64_t>(1, m)) return -12;
+    if (bad_ptr(scale_log2)) return -13;
+    if (bad_ptr(info)) return -15;
+    const size_t fw = trsyl_workspace_size(m, n, opts);
+    if (fw == 0) return -16;
+    if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -17;
+    if (ws_bytes < trsyl_bartels_stewart_workspace_size(m, n, opts)) return -18;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
+    const int mi = (int)m, ni = (int)n;
+    const bool work = m > 0 && n > 0;
+    char *ws = (char *)workspace;
+    double *P = (double *)(ws + align_up(fw));
+    double *part = (double *)(ws + align_up(fw) + align_up(8 * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(n, 1)));
+    char *sc = (char *)part + align_up(8 * (size_t)kNormParts);
+    int32_t *ns = (int32_t *)sc;                 // norm exponent
+    double *nt = (double *)(sc + 8);             // norm sum of squares
+    int64_t *neg = (int64_t *)(sc + 16);         // -shift of the operand being transformed
+    int64_t *tot = (int64_t *)(sc + 24);         // sum of the shifts
+    if (work) {
+        if (launch_fill_zero(tot, sizeof(int64_t), stream) != hipSuccess) return -100;
+        // P = U^T (2^-s0 C), then C = P V
+        if (launch_norm(C, ldc, mi, ni, 0, part, ns, nt, stream) != hipSuccess) return -100;
+        if (launch_norm_shift(ns, nt, neg, tot, stream) != hipSuccess) return -100;
+        if (plain_gemm(mi, ni, mi, U, ldu, 1, C, 1, ldc, neg, P, mi, stream) != hipSuccess) return -100;
+        if (plain_gemm(mi, ni, ni, P, 1, mi, V, 1, ldv, nullptr, C, ldc, stream) != hipSuccess) return -100;
+    }
+    const int rc = trsyl_robust(m, n, At, ldat, Bt, ldbt, C, ldc, scale_log2, scale, info, opts,
+                                workspace, fw, stream_);
+    if (rc != 0) return rc == -100 ? -100 : -16;
+    if (work) {
+        // P = U (2^-s1 Y), then C = P V^T; e += s0 + s1
+        if (launch_norm(C, ldc, mi, ni, 0, part, ns, nt, stream) != hipSuccess) return -100;
+        if (launch_norm_shift(ns, nt, neg, tot, stream) != hipSuccess) return -100;
+        if (plain_gemm(mi, ni, mi, U, 1, ldu, C, 1, ldc, neg, P, mi, stream) != hipSuccess) return -100;
+        if (plain_gemm(mi, ni, ni, P, 1, mi, V, ldv, 1, nullptr, C, ldc, stream) != hipSuccess) return -100;
+        if (launch_add_exponent(scale_log2, scale, tot, stream) != hipSuccess) return -100;
+    }
     return 0;
 }
 

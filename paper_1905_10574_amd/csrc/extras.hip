@@ -60,6 +60,31 @@ __global__ void k_flip_axes(double *W, int64_t ldw, int m, int n, int rows, int 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Power-of-two shift that brings a Frobenius norm 2^s sqrt(t) (launch_norm) to OMEGA = 2^1022 or
+// below: *negshift = -shift, *total += shift.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_norm_shift(const int32_t *s, const double *t, int64_t *negshift, int64_t *total)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t shift = 0;
+    if (*s != 0x7FFFFFFF && *t > 0.0) {
+        const int64_t h = (int64_t)*s + ilogb(sqrt(*t)) + 1;     // 2^h > the norm
+        shift = h > 1022 ? h - 1022 : 0;
+    }
+    *negshift = -shift;
+    *total += shift;
+}
+
+// *e += *add; *scale = 2^-e (0 once e > 1074); scale may be null.
+__global__ void k_add_exponent(int64_t *e, double *scale, const int64_t *add)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t v = *e + *add;
+    *e = v;
+    if (scale) *scale = v > 1074 ? 0.0 : ldexp(1.0, (int)-v);
+}
+
+// ---------------------------------------------------------------------------------------------
 // GEMM.  One workgroup of 512 threads computes a 128 x 128 output tile: wave w = 4 wr + wc owns
 // the 4 x 2 blocks of 16 x 16 at rows 16 (4 wr) .., columns 16 (2 wc) .., accumulated with
 // v_mfma_f64_16x16x4 from double-buffered LDS stages of 16 k.  Operand values outside the
@@ -388,6 +413,19 @@ hipError_t launch_flip_axes(double *W, int64_t ldw, int m, int n, bool rows, boo
 hipError_t launch_flip(double *W, int64_t ldw, int m, int n, hipStream_t s)
 {
     return launch_flip_axes(W, ldw, m, n, true, true, s);
+}
+
+hipError_t launch_norm_shift(const int32_t *s, const double *t, int64_t *negshift, int64_t *total,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm_shift, dim3(1), dim3(64), 0, st, s, t, negshift, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_exponent(int64_t *e, double *scale, const int64_t *add, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_exponent, dim3(1), dim3(64), 0, st, e, scale, add);
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmDesc &g, hipStream_t s)

@@ -51,6 +51,9 @@ hipError_t launch_scale_copy(const double *G, int64_t ldg_, int m, int n, const 
 hipError_t launch_norm(const double *X, int64_t ld, int rows, int cols, int pattern, double *part,
                        int32_t *s, double *t, hipStream_t st);
 hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st);
+hipError_t launch_norm_shift(const int32_t *s, const double *t, int64_t *negshift, int64_t *total,
+                             hipStream_t st);
+hipError_t launch_add_exponent(int64_t *e, double *scale, const int64_t *add, hipStream_t st);
 hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out,
                                  hipStream_t st);
 

@@ -90,3 +90,23 @@ def test_general_form_argument_errors(lib):
     assert call(e=None) == -12
     assert call(info=None) == -14
     assert call(ws=8) == -17
+
+
+def test_bartels_stewart_argument_errors(lib):
+    P, I64 = ctypes.c_void_p, ctypes.c_int64
+    lib.trsyl_bartels_stewart.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, I64, P, I64, P, P, P, P, P,
+                                          ctypes.c_size_t, P]
+    d = ctypes.c_void_p(256)
+
+    def call(m=4, n=4, U=d, ldu=4, At=d, ldat=4, V=d, ldv=4, Bt=d, ldbt=4, C=d, ldc=4, e=d, info=d, ws=1 << 24):
+        return lib.trsyl_bartels_stewart(m, n, U, ldu, At, ldat, V, ldv, Bt, ldbt, C, ldc, e, None, info, None,
+                                         d, ws, None)
+
+    assert call(m=-1) == -1 and call(n=-1) == -2
+    assert call(U=None) == -3 and call(ldu=2) == -4
+    assert call(At=None) == -5 and call(ldat=3) == -6
+    assert call(V=None) == -7 and call(ldv=1) == -8
+    assert call(Bt=None) == -9 and call(ldbt=3) == -10
+    assert call(C=None) == -11 and call(ldc=3) == -12
+    assert call(e=None) == -13 and call(info=None) == -15
+    assert call(ws=8) == -18
