@@ -65,3 +65,11 @@ def test_bartels_stewart_with_scaling(T):
     den = (np.abs(At).sum(1).max() + np.abs(Bt).sum(0).max()) * np.abs(Ys).sum(1).max()
     assert np.isfinite(den) and den > 0
     assert np.abs(R).sum(1).max() / den <= 1e-13
+
+
+@pytest.mark.parametrize("m,n", [(0, 4), (5, 0)])
+def test_bartels_stewart_empty(T, m, n):
+    U, At = np.eye(m), np.eye(m) * 2.0
+    V, Bt = np.eye(n), np.eye(n) * 3.0
+    X, e, info = T.bartels_stewart(U, At, V, Bt, np.zeros((m, n)))
+    assert e == 0 and info == 0 and X.shape == (m, n)

@@ -111,3 +111,12 @@ def test_transposed_problem_with_scaling(T):
     err = np.linalg.norm(_normalised(Y) - _normalised(Yo)) / np.linalg.norm(_normalised(Yo))
     print(f"    e_gpu={e} e_orc={eo} err={err:.2e} oracle spread={spread:.2e}")
     assert err <= max(1e-8, 100 * spread)
+
+
+@pytest.mark.parametrize("m,n", [(0, 5), (6, 0), (0, 0)])
+def test_general_form_empty(T, m, n):
+    A = np.eye(m) * 2.0
+    B = np.eye(n) * 3.0
+    C = np.zeros((m, n))
+    Y, e, info = T.solve_general(A, B, C, "T", "T", -1)
+    assert e == 0 and info == 0 and Y.shape == (m, n)
