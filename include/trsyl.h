@@ -125,6 +125,18 @@ int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, con
                          trsyl_stream_t stream);
 
 /*
+ * Host read-back of a solve's results (the exponent e with alpha = 2^-e, Sec. 2, and the status):
+ * waits for `stream`, then copies *scale_log2, *info and, when scale_host is not NULL, *scale from
+ * device memory into the host variables.
+ *   scale_log2, scale, info           device pointers passed to the solve (scale may be NULL
+ *                                     when scale_host is NULL)
+ *   e_host, scale_host, info_host     host; scale_host may be NULL
+ * Returns 0, -i for a NULL argument i, -100 on a HIP error.
+ */
+int trsyl_sync_result(const int64_t *scale_log2, const double *scale, const int32_t *info,
+                      int64_t *e_host, double *scale_host, int32_t *info_host, trsyl_stream_t stream);
+
+/*
  * General form op(A) Y + isgn Y op(B) = alpha C (the triangular Sylvester equation of Sec. 1 with
  * either coefficient transposed and either sign; with B = A and tranb = 'T' it is the Lyapunov
  * equation A Y + Y A^T = alpha C, which Sec. 1 names as a special case).

@@ -59,6 +59,8 @@ def lib() -> ctypes.CDLL:
         L.trsyl_adjoint_workspace_size.restype = ctypes.c_size_t
         L.trsyl_robust_adjoint.argtypes = L.trsyl_robust.argtypes
         L.trsyl_robust_adjoint.restype = ctypes.c_int
+        L.trsyl_sync_result.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+        L.trsyl_sync_result.restype = ctypes.c_int
         L.trsyl_general_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(Opts)]
         L.trsyl_general_workspace_size.restype = ctypes.c_size_t
         L.trsyl_robust_general.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int32] + list(L.trsyl_robust.argtypes)
@@ -164,6 +166,17 @@ def solve_async(A, B, C, opts: Opts | None = None, *, workspace=None):
         raise RuntimeError(f"trsyl_robust rejected its arguments: {rc}")
     solve_async._keep = (Ac, Bc, ws_keep)  # keep inputs alive until the caller synchronises
     return Yc, e, sc, info
+
+
+def sync_result(e, scale, info, stream=None) -> tuple[int, float, int]:
+    """(e, alpha, info) of a solve enqueued with solve_async, read back by trsyl_sync_result."""
+    eh, sh, ih = ctypes.c_int64(0), ctypes.c_double(0.0), ctypes.c_int32(0)
+    st = stream if stream is not None else _stream(e.device)
+    rc = lib().trsyl_sync_result(e.data_ptr(), scale.data_ptr(), info.data_ptr(), ctypes.byref(eh),
+                                 ctypes.byref(sh), ctypes.byref(ih), st)
+    if rc != 0:
+        raise RuntimeError(f"trsyl_sync_result failed: {rc}")
+    return int(eh.value), float(sh.value), int(ih.value)
 
 
 def solve(A, B, C, *, counters=False, **kw):

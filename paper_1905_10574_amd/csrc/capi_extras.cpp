@@ -75,6 +75,27 @@ int trsyl_robust_adjoint(int64_t m, int64_t n, const double *A, int64_t lda, con
 }
 
 // ---------------------------------------------------------------------------------------------
+// Host read-back of a solve's results: waits for the stream, then copies e, alpha and the status
+// from device memory.
+// ---------------------------------------------------------------------------------------------
+int trsyl_sync_result(const int64_t *scale_log2, const double *scale, const int32_t *info,
+                      int64_t *e_host, double *scale_host, int32_t *info_host, trsyl_stream_t stream_)
+{
+    if (bad_ptr(scale_log2)) return -1;
+    if (bad_ptr(info)) return -3;
+    if (bad_ptr(e_host)) return -4;
+    if (bad_ptr(info_host)) return -6;
+    if (scale_host && bad_ptr(scale)) return -2;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (hipStreamSynchronize(stream) != hipSuccess) return -100;
+    if (hipMemcpy(e_host, scale_log2, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess) return -100;
+    if (hipMemcpy(info_host, info, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return -100;
+    if (scale_host && hipMemcpy(scale_host, scale, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return -100;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
 // General form op(A) Y + isgn Y op(B) = alpha C.  A transposed A is reversed as in the adjoint
 // (Ah = P A^T P, rows of C reversed), a transposed B likewise (Bh = Q B^T Q, columns of C
 // reversed), and isgn = -1 negates the B operand; the forward driver solves

@@ -110,3 +110,15 @@ def test_bartels_stewart_argument_errors(lib):
     assert call(C=None) == -11 and call(ldc=3) == -12
     assert call(e=None) == -13 and call(info=None) == -15
     assert call(ws=8) == -18
+
+
+def test_sync_result_argument_errors(lib):
+    P = ctypes.c_void_p
+    lib.trsyl_sync_result.argtypes = [P, P, P, P, P, P, P]
+    d = ctypes.c_void_p(256)
+    h64, hd, h32 = ctypes.c_int64(0), ctypes.c_double(0.0), ctypes.c_int32(0)
+    assert lib.trsyl_sync_result(None, d, d, ctypes.byref(h64), ctypes.byref(hd), ctypes.byref(h32), None) == -1
+    assert lib.trsyl_sync_result(d, None, d, ctypes.byref(h64), ctypes.byref(hd), ctypes.byref(h32), None) == -2
+    assert lib.trsyl_sync_result(d, d, None, ctypes.byref(h64), ctypes.byref(hd), ctypes.byref(h32), None) == -3
+    assert lib.trsyl_sync_result(d, d, d, None, ctypes.byref(hd), ctypes.byref(h32), None) == -4
+    assert lib.trsyl_sync_result(d, d, d, ctypes.byref(h64), ctypes.byref(hd), None, None) == -6

@@ -172,3 +172,13 @@ def test_empty(T):
     import torch
     Y, e, info = T.solve(np.zeros((0, 0)), np.eye(3), np.zeros((0, 3)))
     assert e == 0 and info == 0 and tuple(Y.shape) == (0, 3)
+
+
+def test_sync_result_reads_back_the_scale(T):
+    """trsyl_sync_result returns the same e, alpha and status as the device tensors (a growth
+    problem, so that e > 0 and alpha = 2^-e is checked as a double too)."""
+    A, B, C = W.growth_problem(2, 96, 80)
+    Yc, e, sc, info = T.solve_async(A, B, C, T.make_opts(tile=32))
+    eh, sh, ih = T.sync_result(e, sc, info)
+    assert (eh, ih) == (int(e.item()), int(info.item()))
+    assert eh > 0 and sh == (math.ldexp(1.0, -eh) if eh <= 1074 else 0.0)
