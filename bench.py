@@ -335,7 +335,7 @@ def main():
         return adjoint_bench(args)
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the batched and single-solve sharding designs are documented, not launched)",
               file=sys.stderr)
         sys.exit(2)
