@@ -120,3 +120,19 @@ def test_general_form_empty(T, m, n):
     C = np.zeros((m, n))
     Y, e, info = T.solve_general(A, B, C, "T", "T", -1)
     assert e == 0 and info == 0 and Y.shape == (m, n)
+
+
+def test_general_form_precision_form(T):
+    """The general form passes the options through: the FP32-update + FP64-refinement form on a
+    transposed, negative-sign problem reaches the dense solver's solution to 1e-10."""
+    rng = np.random.default_rng(21)
+    m, n = 140, 120
+    A = W.quasi_triangular(rng, m, p2x2=0.3, upper=("normal", 1.0 / math.sqrt(m)))
+    B = W.quasi_triangular(rng, n, p2x2=0.3, diag=("uniform", -10.0, -1.0), upper=("normal", 1.0 / math.sqrt(n)))
+    C = rng.standard_normal((m, n))
+    print(f"  gpu solve_general fp32_refine trana=T tranb=N isgn=-1 m={m} n={n}", flush=True)
+    Y, e, info = T.solve_general(A, B, C, "T", "N", -1, tile=64, precision="fp32_refine")
+    Y = Y.cpu().numpy()
+    assert info == 0 and e == 0
+    X = sla.solve_sylvester(A.T, -B, C)
+    assert np.linalg.norm(Y - X) / np.linalg.norm(X) <= 1e-10
