@@ -144,6 +144,21 @@ static void scale_block(int64_t r, int64_t c, double *M, int64_t ld, long s)
         for (int64_t i = 0; i < r; ++i) EL(M, ld, i, j) = ldexp(EL(M, ld, i, j), (int)(-s));
 }
 
+/* Smallest s >= 0 with 2^-s ||M||_inf <= OMEGA, for entries each at most OMEGA (the row sums are
+ * formed from 2^-16 |m_ij|, which cannot overflow for up to 2^16 columns). */
+static long tile_excess_shift(int64_t r, int64_t c, const double *M, int64_t ld)
+{
+    double g = 0.0;
+    for (int64_t i = 0; i < r; ++i) {
+        double t = 0.0;
+        for (int64_t j = 0; j < c; ++j) t += ldexp(fabs(EL(M, ld, i, j)), -16);
+        if (t > g) g = t;
+    }
+    long s = 0;
+    while (ldexp(g, (int)(16 - s)) > OMEGA) ++s;
+    return s;
+}
+
 /* ------------------------------------------------------------------------------------------
  * Small Sylvester solve (Sec. 2.1): A11 Z + Z B11 = beta R with A11 r x r, B11 c x c,
  * r, c in {1, 2}, written as the Kronecker system K vec(Z) = beta vec(R),
@@ -579,6 +594,17 @@ int orc_drsylv(int64_t m, int64_t n, const double *A, int64_t lda, const double 
                            &EL(B, ldb, co[l], co[l]), ldb, &EL(C, ldc, ro[k], co[l]), ldc, smin,
                            &e_syl, &perturbed);
             T.et[k * qt + l] += e_syl;
+            /* Algorithm 2 bounds its 1x1 / 2x2 blocks by OMEGA, Algorithm 4 needs the tile's
+             * ||Y_kl||_inf <= OMEGA (its postcondition and Algorithm 3's precondition): a tile
+             * whose row sums exceed OMEGA is scaled by the smallest power of two that fixes it,
+             * folded into its scale (reading S23) */
+            {
+                const long sx = tile_excess_shift(ro[k + 1] - ro[k], co[l + 1] - co[l], &EL(C, ldc, ro[k], co[l]), ldc);
+                if (sx) {
+                    scale_block(ro[k + 1] - ro[k], co[l + 1] - co[l], &EL(C, ldc, ro[k], co[l]), ldc, sx);
+                    T.et[k * qt + l] += sx;
+                }
+            }
             T.ynorm[k * qt + l] = inf_norm(ro[k + 1] - ro[k], co[l + 1] - co[l], &EL(C, ldc, ro[k], co[l]), ldc);
             int64_t nupd = k + (qt - 1 - l);
 #pragma omp parallel for num_threads(nth) schedule(dynamic, 1) if (nth > 1 && nupd > 1)

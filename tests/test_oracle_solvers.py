@@ -195,7 +195,7 @@ def test_growth_vs_dtrsyl_normalised(orc):
 
 
 def test_paper_scaling_claims(orc):
-    """Sec. 4: mu = m, nu = n needs no scaling; with nu = 1e-2, mu in {1e2, 10} needs none,
+    """Sec. 4 (on the Sec. 3 test matrices): mu = m, nu = n needs no scaling; with nu = 1e-2, mu in {1e2, 10} needs none,
     mu in {1e-3, 1e-7} needs frequent scaling.  (mu = 1, "a few tiles", is parity unpinned.)"""
     m = n = 200
     A, B, C = W.paper_problem(0, m, n, float(m), float(n), p2x2=0.1)
@@ -321,3 +321,68 @@ def test_threads_do_not_change_results(orc):
     Y1, e1, _ = orc.drsylv(A, B, C, 32, 24, threads=1)
     Y4, e4, _ = orc.drsylv(A, B, C, 32, 24, threads=4)
     assert e1 == e4 and np.array_equal(Y1, Y4)
+
+
+@pytest.mark.parametrize("m,n", SMALL_SHAPES)
+def test_alg1_matches_kronecker_brute_force(orc, m, n):
+    """Algorithm 1 (Sec. 1, no scaling) on well-separated inputs with 2x2 blocks equals the
+    Kronecker solution: a dropped or misplaced column update (Y above the block) or row update
+    (Y right of the block), or a wrong small solve, moves the result by O(1)."""
+    for seed in range(3):
+        A, B, C = W.separated_problem(seed * 17 + m * 5 + n, m, n, p2x2=0.3, upper_scale="none")
+        X = kron_solve(A, B, C)
+        Y = orc.nonrobust_syl(A, B, C)
+        assert rel(Y, X) <= 1e-12
+
+
+def test_alg1_agrees_with_alg2_when_no_scaling_happens(orc):
+    """Where Algorithm 2 chooses no scaling (e = 0) it performs Algorithm 1's arithmetic up to the
+    pivoting of the small solves, so both must agree to rounding."""
+    A, B, C = W.config_small(1)
+    Y2, e2, rc = orc.robust_syl(A, B, C)
+    assert rc == 0 and e2 == 0
+    assert rel(orc.nonrobust_syl(A, B, C), Y2) <= 1e-13
+
+
+def test_smin_closed_forms(orc):
+    """smin = max(2^-52 max|A, B|, DBL_MIN) over the entries on or above the first subdiagonal
+    (reading S10 of the design): checked on inputs whose value is known in closed form."""
+    A = np.diag([2.0 ** 10, 3.0, -5.0])
+    B = np.diag([2.0 ** 3, 1.0])
+    assert orc.smin(A, B) == 2.0 ** (10 - 52)
+    # the largest entry may sit in B, in a strictly upper position or on the subdiagonal
+    B2 = B.copy(); B2[0, 1] = -2.0 ** 40
+    assert orc.smin(A, B2) == 2.0 ** (40 - 52)
+    A2 = np.array([[1.0, 0.0], [2.0 ** 20, 1.0]])          # a 2x2 block's subdiagonal entry
+    assert orc.smin(A2, np.eye(1)) == 2.0 ** (20 - 52)
+    # entries below the first subdiagonal are never read
+    A3 = np.diag([1.0, 1.0, 1.0]); A3[2, 0] = 2.0 ** 900
+    assert orc.smin(A3, np.eye(2)) == 2.0 ** -52
+    # tiny matrices: the floor DBL_MIN
+    assert orc.smin(np.diag([2.0 ** -1000]), np.diag([2.0 ** -1010])) == 2.0 ** -1022
+    assert orc.smin(np.zeros((2, 2)), np.zeros((1, 1))) == 2.0 ** -1022
+
+
+def tile_norms(Y, ro, co):
+    return np.array([[np.abs(Y[ro[k]:ro[k + 1], co[l]:co[l + 1]]).sum(axis=1).max(initial=0.0)
+                      for l in range(len(co) - 1)] for k in range(len(ro) - 1)])
+
+
+def test_tile_norms_bounded_by_omega(orc):
+    """Alg. 4 (Sec. 2.2) promises ||Y_kl||_inf <= Omega for every tile, but Alg. 2 bounds only its
+    1x1 / 2x2 blocks.  With diagonal A, B (a + b = 2^-3 everywhere) and C entries near Omega/256,
+    the exact solution is X = 8 C, whose 128-wide tiles have row sums about 3.2 Omega: the robust
+    solve must return Y = 2^-e X exactly with e = 2, the smallest exponent that brings every tile
+    norm to Omega or below (reading S23)."""
+    m = n = 256
+    t = 128
+    A = np.diag(np.full(m, 2.0 ** -4))
+    B = np.diag(np.full(n, 2.0 ** -4))
+    C = np.ldexp(np.random.default_rng(0).uniform(0.5, 1.0, (m, n)), 1022 - 8)
+    Y, e, rc = orc.drsylv(A, B, C, t)
+    assert rc == 0 and e == 2
+    assert np.array_equal(Y, np.ldexp(8 * C, -2))
+    ro = orc.tile_offsets(A, t)
+    co = orc.tile_offsets(B, t)
+    assert (tile_norms(Y, ro, co) <= OMEGA).all()
+    assert (tile_norms(np.ldexp(8 * C, -1), ro, co) > OMEGA).any()     # e = 1 would not do
