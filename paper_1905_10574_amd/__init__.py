@@ -120,14 +120,20 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def colmajor(X: torch.Tensor, device=None) -> torch.Tensor:
+def colmajor(X: torch.Tensor, device=None, fresh: bool = False) -> torch.Tensor:
     """Column-major float64 copy on the device, returned as its transposed (row-major) storage
-    tensor S with S.t() == X; S.data_ptr() is the column-major buffer with ld = X.shape[0]."""
+    tensor S with S.t() == X; S.data_ptr() is the column-major buffer with ld = X.shape[0].
+    When X already is a column-major float64 tensor on that device, S shares X's storage; with
+    fresh=True (operands the library overwrites) S is always a new buffer, so the caller's
+    tensor is never written."""
     if not isinstance(X, torch.Tensor):
         X = torch.as_tensor(X)
     if device is None:
         device = X.device if X.is_cuda else torch.device("cuda")
-    return X.to(device=device, dtype=torch.float64).t().contiguous()
+    S = X.to(device=device, dtype=torch.float64).t().contiguous()
+    if fresh and S.numel() > 0 and S.untyped_storage().data_ptr() == X.untyped_storage().data_ptr():
+        S = S.clone()
+    return S
 
 
 def _aligned_workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
@@ -148,7 +154,7 @@ def solve_async(A, B, C, opts: Opts | None = None, *, workspace=None):
     Ac = colmajor(A)
     dev = Ac.device
     Bc = colmajor(B, dev)
-    Yc = colmajor(C, dev)
+    Yc = colmajor(C, dev, fresh=True)
     m, n = Yc.shape[1], Yc.shape[0]
     e = torch.zeros(1, dtype=torch.int64, device=dev)
     sc = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -223,7 +229,7 @@ def adjoint_async(A, B, W, opts: Opts | None = None):
     Ac = colmajor(A)
     dev = Ac.device
     Bc = colmajor(B, dev)
-    Gc = colmajor(W, dev)
+    Gc = colmajor(W, dev, fresh=True)
     m, n = Gc.shape[1], Gc.shape[0]
     e = torch.zeros(1, dtype=torch.int64, device=dev)
     sc = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -253,7 +259,7 @@ def general_async(A, B, C, trana="N", tranb="N", isgn=1, opts: Opts | None = Non
     Ac = colmajor(A)
     dev = Ac.device
     Bc = colmajor(B, dev)
-    Yc = colmajor(C, dev)
+    Yc = colmajor(C, dev, fresh=True)
     m, n = Yc.shape[1], Yc.shape[0]
     e = torch.zeros(1, dtype=torch.int64, device=dev)
     sc = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -288,7 +294,7 @@ def bartels_stewart(U, At, V, Bt, C, **kw):
     opts = make_opts(**kw)
     Uc = colmajor(U)
     dev = Uc.device
-    Atc, Vc, Btc, Xc = colmajor(At, dev), colmajor(V, dev), colmajor(Bt, dev), colmajor(C, dev)
+    Atc, Vc, Btc, Xc = colmajor(At, dev), colmajor(V, dev), colmajor(Bt, dev), colmajor(C, dev, fresh=True)
     m, n = Xc.shape[1], Xc.shape[0]
     e = torch.zeros(1, dtype=torch.int64, device=dev)
     sc = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -390,7 +396,7 @@ def _batched_async(As, Bs, Cs, tiles, opts, adjoint):
     Acs = [colmajor(A) for A in As]
     dev = Acs[0].device if count else torch.device("cuda")
     Bcs = [colmajor(B, dev) for B in Bs]
-    Ycs = [colmajor(C, dev) for C in Cs]
+    Ycs = [colmajor(C, dev, fresh=True) for C in Cs]
     ms = [Y.shape[1] for Y in Ycs]
     ns = [Y.shape[0] for Y in Ycs]
     if isinstance(tiles, str) and tiles == "auto":

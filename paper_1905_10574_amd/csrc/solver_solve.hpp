@@ -573,6 +573,22 @@ __device__ double tile_norm_copy(const double *src, int64_t lsrc, const DevView 
     return wg_max(v, L.red);
 }
 
+// The smallest s >= 0 with 2^-s ||Y||_inf <= OMEGA for an mr x nc tile (ld ldy) whose entries are
+// at most OMEGA each: row sums are formed from 2^-16 |y|, which cannot overflow.
+__device__ int tile_excess_shift(const double *Y, int64_t ldy, int mr, int nc, SolveLds &L)
+{
+    double g = 0.0;
+    for (int r = threadIdx.x; r < mr; r += kThreads) {
+        double t = 0.0;
+        for (int c = 0; c < nc; ++c) t += ldexp(fabs(ldg(Y + (int64_t)c * ldy + r)), -16);
+        g = fmax(g, t);
+    }
+    g = wg_max(g, L.red);
+    int s = 0;
+    while (s < 2200 && ldexp(g, 16 - s) > kOmega) ++s;
+    return s;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Algorithm 2 as printed, on one tile, by the whole workgroup.  Returns the exponent of beta.
 // ---------------------------------------------------------------------------------------------
@@ -780,6 +796,16 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
             e_syl = tile_solve_robust(P, Ad, Bd, scratch, mr, mr, nc, smin, L, &pert);
         }
         nrm = tile_norm_copy(scratch, mr, &vY, P.ldc, mr, nc, L);   // publish the tile, exact norm
+        // Algorithm 2 bounds the tile's 1x1 / 2x2 blocks only; Algorithm 4 needs ||Y_kl||_inf <=
+        // OMEGA (its postcondition and Algorithm 3's precondition).  A tile above it (or whose
+        // row sums overflowed) is scaled by the smallest power of two that restores the bound,
+        // folded into the tile's scale, and published again.
+        if (uniform(!(nrm <= kOmega) ? 1 : 0)) {
+            const int sx = uniform(tile_excess_shift(scratch, mr, mr, nc, L));
+            scale_tile(scratch, mr, mr, nc, sx);
+            nrm = tile_norm_copy(scratch, mr, &vY, P.ldc, mr, nc, L);
+            e_syl += sx;
+        }
         TRSYL_STAMP(stamp, 3);
     }
     if (pert) set_status(P.status, kPerturbed);

@@ -22,14 +22,23 @@ namespace trsyl {
 constexpr int kUS = 146;
 constexpr int kUK = 16;               // k per stage
 
+// FP64 stages loaded straight into LDS: As[k][m] (k-major, row stride kUS) and Bs[n][k]
+// (column-major like the operand, 16 k per column plus one 16-byte pad slot, stride kBS), in a
+// ring of kDStages buffers so that two stages are in flight while one is multiplied.
+constexpr int kDStages = 3;
+constexpr int kBS = 18;
+constexpr int kDA = kUK * kUS;        // doubles per A stage
+constexpr int kDB = 144 * kBS;        // doubles per B stage
+constexpr int kDStage = kDA + kDB;
+
 struct UpdateLds {
-    // operand stages, viewed as T As[2][kUK][kUS] followed by T Bs[2][kUK][kUS] (T = double, or
-    // float for the FP32 form): Aop(m, k) of the pass rows and Bop(k, n) of the pass columns,
-    // k-major
-    double stage[2 * 2 * kUK * kUS];
+    // operand stages.  FP64: kDStages x (As, Bs) as above.  FP32 form: T As[2][kUK][kUS] followed
+    // by T Bs[2][kUK][kUS], both k-major, staged through registers.
+    double stage[kDStages * kDStage];
     double rs[kWaves][kMaxTile + 3];  // per-wave partial absolute row sums of the slab
     double red[kWaves];
 };
+static_assert(2 * 2 * kUK * kUS <= kDStages * kDStage, "FP32 stages fit the FP64 ring");
 template <class T> __device__ __forceinline__ T *stage_A(UpdateLds &L, int buf)
 {
     return reinterpret_cast<T *>(L.stage) + (size_t)buf * kUK * kUS;
@@ -357,6 +366,306 @@ __device__ __forceinline__ void update_passes(const Plan &P, const double *Aop, 
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// FP64 passes with direct-to-LDS operand stages (gfx950 global_load_lds_dwordx4: lane l of a wave
+// writes the 16 bytes it loads to LDS at base + 16 l, without passing through registers).
+//
+// A stage (16 k) is issued by every wave: A rows k = 2w, 2w + 1 (one instruction for m < 128 and
+// one of 8 lanes for m = 128..143), and B slots 64 i + lane for i = w, w + 8, w + 16 (< 21): slot
+// s covers column n = s / 9, k = 2 (s % 9) .. + 1, with s % 9 == 8 the pad.  Lanes whose k range
+// lies at or beyond K, whose column is past the pass, or that fill a pad read 16 bytes of zeros;
+// when K is odd the B slot holding k = K - 1 also reads zeros and that one value is written into
+// LDS separately (a 16-byte read would cross the source tile).  A rows past the pass are loaded
+// (they only feed output rows that are not stored) or read as zeros.
+//
+// Waits are explicit: loads return in issue order, so `s_waitcnt vmcnt(n)` with n the loads issued
+// after a stage completes it.  The barriers between stages wait only for LDS traffic (a workgroup
+// fence would also wait for the two stages still in flight).
+// ---------------------------------------------------------------------------------------------
+// Target block (brow, bcol) of a pass loaded into an FP64 accumulator in the MFMA result layout
+// (element i of lane (r, q): row m0 + 16 brow + r, column n0 + 16 bcol + q + 4 i); entries past
+// the pass read as zero.
+__device__ __forceinline__ void load_target_acc(d4 &acc, const DevView &Ct, int64_t ldc, int m0, int Mp, int n0,
+                                                int Np, int brow, int bcol)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int mm = m0 + 16 * brow + r;
+    const bool mok = mm < m0 + Mp;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int nn = n0 + 16 * bcol + q + 4 * i;
+        const bool ok = mok && nn < n0 + Np;
+        const double v = ld_dev(Ct, (int64_t)(ok ? nn : n0) * ldc + (ok ? mm : m0));
+        acc[i] = ok ? v : 0.0;
+    }
+}
+// -2^sh x, element by element (sh <= 0: an exact power-of-two scaling, the target's share of
+// Algorithm 3's delta / gamma)
+__device__ __forceinline__ d4 neg_scale4(d4 x, int sh)
+{
+    d4 y;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = -(sh ? ldexp(x[i], sh) : x[i]);
+    return y;
+}
+// Stores D = -acc on the valid entries of the block (device scope) and adds the block's absolute
+// row sums to rs[row - rbase].
+__device__ __forceinline__ void store_neg_acc(const d4 &acc, const DevView &Ct, int64_t ldc, int m0, int Mp, int n0,
+                                              int Np, int brow, int bcol, double *rs, int rbase)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int mm = m0 + 16 * brow + r;
+    const bool mok = mm < m0 + Mp;
+    double rsum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int nn = n0 + 16 * bcol + q + 4 * i;
+        if (mok && nn < n0 + Np) {
+            const double d = -acc[i];
+            st_dev(Ct, (int64_t)nn * ldc + mm, d);
+            rsum += fabs(d);
+        }
+    }
+    rsum += __shfl_xor(rsum, 16);
+    rsum += __shfl_xor(rsum, 32);
+    if (q == 0 && mok) rs[mm - rbase] += rsum;
+}
+
+__device__ __align__(16) const double g_zero16[2] = {0.0, 0.0};
+
+typedef __attribute__((address_space(1))) const void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+// s_waitcnt vmcnt(n) (0 <= n < 16) leaving the other counters alone.  n is wave-uniform.
+__device__ __forceinline__ void wait_vm(int n)
+{
+#define TRSYL_VM(N) case N: __builtin_amdgcn_s_waitcnt((N) | (0x7 << 4) | (0xF << 8)); break;
+    switch (n) {
+        TRSYL_VM(0) TRSYL_VM(1) TRSYL_VM(2) TRSYL_VM(3) TRSYL_VM(4) TRSYL_VM(5) TRSYL_VM(6)
+        TRSYL_VM(7) TRSYL_VM(8) TRSYL_VM(9) TRSYL_VM(10) TRSYL_VM(11) TRSYL_VM(12) TRSYL_VM(13)
+        TRSYL_VM(14)
+        default: __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8)); break;
+    }
+#undef TRSYL_VM
+}
+
+// Workgroup barrier that orders LDS traffic only: this wave's LDS accesses have completed, and the
+// compiler moves no memory access across it.  Global loads in flight stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xF | (0x7 << 4) | (0x0 << 8) | (0x3 << 14));   // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ double *dstage_A(UpdateLds &L, int buf) { return L.stage + (size_t)buf * kDStage; }
+__device__ __forceinline__ double *dstage_B(UpdateLds &L, int buf) { return L.stage + (size_t)buf * kDStage + kDA; }
+
+// Issue stage kc (k in [kc, kc + 16)) of a pass into ring buffer `buf`.  PA / PB: cache policy
+// of the A / B operand (device scope for the solved tile, which other workgroups write).
+template <int PA, int PB>
+__device__ __forceinline__ void dma_stage(UpdateLds &L, int buf, const double *Aop, int64_t lda, int m0, int Mp,
+                                          bool tailA, const double *Bop, int64_t ldb, int n0, int Np, int kc, int K)
+{
+    const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    double *stA = dstage_A(L, buf), *stB = dstage_B(L, buf);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int kr = 2 * w + h, k = kc + kr;
+        const bool kin = k < K;
+        {
+            const int m = 2 * lane;
+            const double *src = (kin && m < Mp) ? Aop + (int64_t)k * lda + m0 + m : g_zero16;
+            __builtin_amdgcn_global_load_lds((gvoid_t *)src, (lvoid_t *)(stA + kr * kUS), 16, 0, PA);
+        }
+        if (tailA) {
+            if (lane < 8) {
+                const int m = 128 + 2 * lane;
+                const double *src = (kin && m < Mp) ? Aop + (int64_t)k * lda + m0 + m : g_zero16;
+                __builtin_amdgcn_global_load_lds((gvoid_t *)src, (lvoid_t *)(stA + kr * kUS + 128), 16, 0, PA);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int i = w + 8 * t;
+        if (i < 21) {
+            const int s = 64 * i + lane;
+            const int n = s / 9, j = s - 9 * n;
+            const int k = kc + 2 * j;
+            const bool ok = j < 8 && n < Np && k + 1 < K;
+            const double *src = ok ? Bop + (int64_t)(n0 + n) * ldb + k : g_zero16;
+            if (i < 20 || lane < 16)
+                __builtin_amdgcn_global_load_lds((gvoid_t *)src, (lvoid_t *)(stB + 128 * i), 16, 0, PB);
+        }
+    }
+}
+
+// One update slab in FP64 (see update_passes for the block layout of the waves).  `decide` runs
+// the scale decision of Algorithm 3 and returns (shC, shY); it is called once, after the first
+// pass's first two stages have been issued, so its loads overlap theirs.  The solved tile's
+// stage is multiplied by 2^shY in LDS when shY != 0.
+template <bool COL, class Decide>
+__device__ __forceinline__ void update_passes_f64(const Plan &P, const double *Aop, int64_t lda, const double *Bop,
+                                                  int64_t ldb, int K, double *Ct, int rows, int cols, int rb_lo,
+                                                  int nrb, UpdateLds &L, uint64_t *ustamp, Decide decide)
+{
+    constexpr int PA = COL ? 0 : kPolicyDevice, PB = COL ? kPolicyDevice : 0;
+    const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int wr = w >> 2, wc = w & 3;
+    const int ncbt = (cols + 15) >> 4;
+    const int ngr = block_groups(nrb), ngc = block_groups(ncbt);
+    const int nkc = (K + kUK - 1) / kUK;
+    const bool oddK = (K & 1) != 0;
+    const DevView vB = dev_view(Bop, ldb, K, cols);
+    const DevView vC = dev_view(Ct, P.ldc, rows, cols);
+    const int nB = w < 5 ? 3 : 2;
+    int shC = 0, shY = 0;
+    bool decided = false;
+    for (int gr = 0; gr < ngr; ++gr) {
+        for (int gc = 0; gc < ngc; ++gc) {
+            const int R = group_size(nrb, gr, ngr), Cc = group_size(ncbt, gc, ngc);
+            const int m0 = 16 * (rb_lo + 8 * gr), n0 = 16 * 8 * gc;
+            const int Mp = (m0 + 16 * R < rows ? m0 + 16 * R : rows) - m0;
+            const int Np = (n0 + 16 * Cc < cols ? n0 + 16 * Cc : cols) - n0;
+            const int R8 = R < 8 ? R : 8, C8 = Cc < 8 ? Cc : 8;
+            const int nrm = R8 - 4 * wr < 0 ? 0 : (R8 - 4 * wr > 4 ? 4 : R8 - 4 * wr);
+            const int ncm = C8 - 2 * wc < 0 ? 0 : (C8 - 2 * wc > 2 ? 2 : C8 - 2 * wc);
+            const int xrow = R == 9 ? Cc : 0;
+            const int nx = xrow + (Cc == 9 ? R8 : 0);
+            int xr[3], xc[3];
+            int nxw = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int e = w + kWaves * j;
+                xr[j] = e < xrow ? 8 : e - xrow;
+                xc[j] = e < xrow ? e : 8;
+                if (e < nx) nxw = j + 1;
+            }
+            const bool tailA = uniform(Mp > 128 ? 1 : 0) != 0;
+            const bool full = nrm == 4 && ncm == 2;              // all eight main blocks live
+            const int Lw = 2 + (tailA ? 2 : 0) + nB;             // loads per stage of this wave
+            // every wave has left the previous pass's buffers
+            lds_barrier();
+            // k = K - 1 of each B column when K is odd (issued first: the stage waits cover it)
+            double fix = 0.0;
+            if (oddK && (int)threadIdx.x < Np) {
+                const int64_t idx = (int64_t)(n0 + threadIdx.x) * ldb + (K - 1);
+                fix = COL ? ld_dev(vB, idx) : ldg(Bop + idx);
+            }
+            // the target's blocks go straight into the accumulators (issued first, so that they,
+            // the first two operand stages and the scale decision share one round trip); the
+            // product is then accumulated onto -2^shC C and the result is the negated sum
+            d4 acc[4][2], accx[3];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    acc[a][b] = zero4();
+                    if (a < nrm && b < ncm) load_target_acc(acc[a][b], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
+                }
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                accx[x] = zero4();
+                if (x < nxw) load_target_acc(accx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
+            }
+            dma_stage<PA, PB>(L, 0, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np, 0, K);
+            if (nkc > 1) dma_stage<PA, PB>(L, 1, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np, kUK, K);
+            if (!decided) {
+                const int2 d = decide();
+                shC = uniform(d.x);
+                shY = uniform(d.y);
+                decided = true;
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) acc[a][b] = neg_scale4(acc[a][b], shC);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) accx[x] = neg_scale4(accx[x], shC);
+            if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[2] = wall_clock64();
+            for (int c = 0; c < nkc; ++c) {
+                const int buf = c % kDStages;
+                wait_vm(c + 1 < nkc ? Lw : 0);
+                lds_barrier();
+                const bool last = c == nkc - 1;
+                if (shY != 0) {
+                    // the solved tile enters the product times 2^shY (Algorithm 3's delta / alpha)
+                    double *sh = COL ? dstage_B(L, buf) : dstage_A(L, buf);
+                    const int cnt = COL ? kDB : kDA;
+                    for (int t = threadIdx.x; t < cnt; t += kThreads) sh[t] = ldexp(sh[t], shY);
+                    if (last && oddK) lds_barrier();
+                }
+                if (last && oddK) {
+                    if ((int)threadIdx.x < Np)
+                        dstage_B(L, buf)[threadIdx.x * kBS + (K - 1 - kUK * c)] = (COL && shY) ? ldexp(fix, shY) : fix;
+                }
+                if (shY != 0 || (last && oddK)) lds_barrier();
+                if (c + 2 < nkc)
+                    dma_stage<PA, PB>(L, (c + 2) % kDStages, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np,
+                                      kUK * (c + 2), K);
+                const double *As = dstage_A(L, buf), *Bs = dstage_B(L, buf);
+                // this lane's 4 k of each of its B column blocks are adjacent: two 16-byte reads
+                double bq[2][4];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double2 *bp = reinterpret_cast<const double2 *>(Bs + (16 * (2 * wc + b) + r) * kBS + 4 * q);
+                    const double2 x0 = bp[0], x1 = bp[1];
+                    bq[b][0] = x0.x; bq[b][1] = x0.y; bq[b][2] = x1.x; bq[b][3] = x1.y;
+                }
+                if (full) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = 4 * q + j;
+                        double av[4];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) av[a] = As[k * kUS + 16 * (4 * wr + a) + r];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bq[b][j], av[a], acc[a][b]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = 4 * q + j;
+                        double av[4];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) av[a] = As[k * kUS + 16 * (4 * wr + a) + r];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int b = 0; b < 2; ++b)
+                                if (a < nrm && b < ncm) acc[a][b] = mfma16(bq[b][j], av[a], acc[a][b]);
+                    }
+                }
+                if (nxw > 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = 4 * q + j;
+#pragma unroll
+                        for (int x = 0; x < 3; ++x)
+                            if (x < nxw)
+                                accx[x] = mfma16(Bs[(16 * xc[x] + r) * kBS + k], As[k * kUS + 16 * xr[x] + r], accx[x]);
+                    }
+                }
+            }
+            if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[3] = wall_clock64();
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (a < nrm && b < ncm)
+                        store_neg_acc(acc[a][b], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b, L.rs[w], 16 * rb_lo);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+                if (x < nxw) store_neg_acc(accx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x], L.rs[w], 16 * rb_lo);
+        }
+    }
+}
+
 __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int S_, int u_, int slab_,
                                        UpdateLds &L, uint64_t *ustamp)
 {
@@ -371,29 +680,28 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
     const int r0 = uniform(P.rowoff[ti]), rows = uniform(P.rowoff[ti + 1]) - r0;
     const int c0 = uniform(P.coloff[tl]), cols = uniform(P.coloff[tl + 1]) - c0;
 
-    // scale decision (identical in every slab of this update)
-    const int VS = tile_updates(P, S) + 1;
-    const int eC = tile_exp_at(P, T, u);
-    const int eY = tile_exp_at(P, S, VS);
-    const double cn = tile_norm_at(P, T, u);
-    const double yn = tile_norm_at(P, S, VS);
-    const int emax = eC > eY ? eC : eY;
-    const double cs = ldexp(cn, eC - emax), ys = ldexp(yn, eY - emax);
     const bool colu = kind == kTaskColUpdate;
-    double tn;
-    int K;
-    if (colu) {      // target (ti, tl) -= A(ti, si) * Y(si, tl)
-        tn = P.anorm[(size_t)ti * P.pt + si];
-        K = uniform(P.rowoff[si + 1] - P.rowoff[si]);
-    } else {         // target (ti, tl) -= Y(ti, sl) * B(sl, tl)
-        tn = P.bnorm[(size_t)sl * P.qt + tl];
-        K = uniform(P.coloff[sl + 1] - P.coloff[sl]);
-    }
-    const int s = colu ? protect_update(cs, tn, ys) : protect_update(cs, ys, tn);
-    const int enew = emax + s;
-    const int shC = uniform(eC - enew);       // <= 0
-    const int shY = uniform(eY - enew);       // <= 0
-    if (threadIdx.x == 0 && slab == 0 && (shC != 0 || shY != 0)) atomicAdd(&P.stats[1], 1u);
+    const int K = colu ? uniform(P.rowoff[si + 1] - P.rowoff[si]) : uniform(P.coloff[sl + 1] - P.coloff[sl]);
+    const double tn = colu ? P.anorm[(size_t)ti * P.pt + si] : P.bnorm[(size_t)sl * P.qt + tl];
+    const int VS = tile_updates(P, S) + 1;
+
+    // scale decision (identical in every slab of this update): returns (shC, shY) and sets enew
+    int enew = 0;
+    double yn = 0.0;
+    auto decide = [&]() -> int2 {
+        const int eC = tile_exp_at(P, T, u);
+        const int eY = tile_exp_at(P, S, VS);
+        const double cn = tile_norm_at(P, T, u);
+        yn = tile_norm_at(P, S, VS);
+        const int emax = eC > eY ? eC : eY;
+        const double cs = ldexp(cn, eC - emax), ys = ldexp(yn, eY - emax);
+        const int sp = colu ? protect_update(cs, tn, ys) : protect_update(cs, ys, tn);
+        enew = uniform(emax + sp);
+        const int shC_ = uniform(eC - enew);       // <= 0
+        const int shY_ = uniform(eY - enew);       // <= 0
+        if (threadIdx.x == 0 && slab == 0 && (shC_ != 0 || shY_ != 0)) atomicAdd(&P.stats[1], 1u);
+        return make_int2(shC_, shY_);
+    };
 
     int rb_lo, rb_hi;
     slab_rows(rows, P.slabs, slab, &rb_lo, &rb_hi);
@@ -403,12 +711,25 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
     __syncthreads();
     if (ustamp && threadIdx.x == 0) ustamp[1] = wall_clock64();
 
-    if (rows > 0 && cols > 0 && nrb > 0 && K > 0) {
-        const int k0 = colu ? uniform(P.rowoff[si]) : uniform(P.coloff[sl]);
-        const double *Aop = colu ? P.A + (int64_t)k0 * P.lda + r0 : P.C + (int64_t)k0 * P.ldc + r0;
-        const double *Bop = colu ? P.C + (int64_t)c0 * P.ldc + k0 : P.B + (int64_t)c0 * P.ldb + k0;
-        const int64_t lda_ = colu ? P.lda : P.ldc, ldb_ = colu ? P.ldc : P.ldb;
-        if (P.flags & kFlagF32Updates) {
+    const bool gemm = rows > 0 && cols > 0 && nrb > 0 && K > 0;
+    const int k0 = colu ? uniform(P.rowoff[si]) : uniform(P.coloff[sl]);
+    const double *Aop = colu ? P.A + (int64_t)k0 * P.lda + r0 : P.C + (int64_t)k0 * P.ldc + r0;
+    const double *Bop = colu ? P.C + (int64_t)c0 * P.ldc + k0 : P.B + (int64_t)c0 * P.ldb + k0;
+    const int64_t lda_ = colu ? P.lda : P.ldc, ldb_ = colu ? P.ldc : P.ldb;
+    int shC = 0;
+    if (gemm && !(P.flags & kFlagF32Updates)) {
+        // FP64: the decision runs inside, overlapped with the first operand stages
+        int shY = 0;
+        auto dec = [&]() -> int2 { const int2 d = decide(); shC = d.x; shY = d.y; return d; };
+        if (colu)
+            update_passes_f64<true>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+        else
+            update_passes_f64<false>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+    } else {
+        const int2 d = decide();
+        shC = uniform(d.x);
+        const int shY = uniform(d.y);
+        if (gemm) {
             // normalise both operands to entries below 1 (their infinity norms bound every entry)
             // and take the product back by the shifts plus the update's scale of Y_S
             const int sT = tn > 0.0 ? -(ilogb(tn) + 1) : 0;
@@ -418,25 +739,25 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
                 update_passes<true, float>(P, Aop, lda_, Bop, ldb_, K, sT, sY, shP, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
             else
                 update_passes<false, float>(P, Aop, lda_, Bop, ldb_, K, sY, sT, shP, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
-        } else {
-            if (colu)
-                update_passes<true, double>(P, Aop, lda_, Bop, ldb_, K, 0, shY, 0, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
-            else
-                update_passes<false, double>(P, Aop, lda_, Bop, ldb_, K, shY, 0, 0, shC, Ct, rows, cols, rb_lo, nrb, L, ustamp);
-        }
-    } else if (rows > 0 && cols > 0 && nrb > 0 && shC != 0) {
-        // an empty source still rescales the target to the common exponent
-        const int srows = (16 * rb_hi < rows ? 16 * rb_hi : rows) - 16 * rb_lo;
-        for (int t = threadIdx.x; t < srows; t += kThreads) {
-            double rs = 0.0;
-            const DevView vC = dev_view(Ct, P.ldc, rows, cols);
-            for (int nn = 0; nn < cols; ++nn) {
-                const int64_t idx = (int64_t)nn * P.ldc + 16 * rb_lo + t;
-                const double d = ldexp(ld_dev(vC, idx), shC);
-                st_dev(vC, idx, d);
-                rs += fabs(d);
+        } else if (rows > 0 && cols > 0 && nrb > 0) {
+            // an empty source (a tile emptied by a boundary that dodged a 2x2 block) leaves the
+            // product out, but the target still moves to the common exponent and its next
+            // version still needs its exact row sums
+            const int srows = (16 * rb_hi < rows ? 16 * rb_hi : rows) - 16 * rb_lo;
+            for (int t = threadIdx.x; t < srows; t += kThreads) {
+                double rs = 0.0;
+                const DevView vC = dev_view(Ct, P.ldc, rows, cols);
+                for (int nn = 0; nn < cols; ++nn) {
+                    const int64_t idx = (int64_t)nn * P.ldc + 16 * rb_lo + t;
+                    double d = ld_dev(vC, idx);
+                    if (shC != 0) {
+                        d = ldexp(d, shC);
+                        st_dev(vC, idx, d);
+                    }
+                    rs += fabs(d);
+                }
+                L.rs[0][t] = rs;
             }
-            L.rs[0][t] = rs;
         }
     }
     __syncthreads();

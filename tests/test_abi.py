@@ -122,3 +122,18 @@ def test_sync_result_argument_errors(lib):
     assert lib.trsyl_sync_result(d, d, None, ctypes.byref(h64), ctypes.byref(hd), ctypes.byref(h32), None) == -3
     assert lib.trsyl_sync_result(d, d, d, None, ctypes.byref(hd), ctypes.byref(h32), None) == -4
     assert lib.trsyl_sync_result(d, d, d, ctypes.byref(h64), ctypes.byref(hd), None, None) == -6
+
+
+def test_colmajor_fresh_never_aliases_the_callers_tensor():
+    """A column-major float64 operand is passed through without a copy, except for operands the
+    library overwrites (C / W), which always get a buffer of their own."""
+    import torch
+    import paper_1905_10574_amd as T
+    X = torch.arange(12, dtype=torch.float64).reshape(3, 4).t().contiguous().t()   # column-major
+    S = T.colmajor(X, torch.device("cpu"))
+    assert S.data_ptr() == X.data_ptr() and torch.equal(S.t(), X)
+    F = T.colmajor(X, torch.device("cpu"), fresh=True)
+    assert F.data_ptr() != X.data_ptr() and torch.equal(F.t(), X)
+    R = torch.arange(12, dtype=torch.float64).reshape(3, 4)                     # row-major
+    F2 = T.colmajor(R, torch.device("cpu"), fresh=True)
+    assert F2.data_ptr() != R.data_ptr() and torch.equal(F2.t(), R)
