@@ -65,7 +65,10 @@ typedef struct trsyl_opts {
     int32_t scheduler;   /* enum trsyl_scheduler */
     int32_t slabs;       /* row slabs per tile update task; 0 = default (1: whole tiles) */
     int32_t max_sweeps;  /* refinement sweeps for TRSYL_FP32_REFINE; 0 = default 3, < 0 = none */
-    double refine_tol;   /* eq. (9) target for TRSYL_FP32_REFINE; 0 = default 1e-13 */
+    double refine_tol;   /* TRSYL_FP32_REFINE: each sweep first evaluates eq. (9) (Sec. 3) of
+                            the current (Y, alpha) on the device; once it is <= refine_tol the
+                            remaining sweeps do nothing (no host synchronisation).
+                            0 = default 1e-13 */
     int32_t workers;     /* persistent workgroups; 0 = one per compute unit */
     int32_t flags;       /* bit 0: force the robust (non-speculative) tile solve */
     void *profile_events; /* optional host pointer to two caller-owned hipEvent_t: the library
@@ -80,7 +83,8 @@ typedef struct trsyl_opts {
                              rescaled the target or the solved tile (scaling events of
                              RobustUpdate, Algorithm 3), [2] tile solves whose unscaled
                              certificate failed, so that the leaf-tiled robust solve ran,
-                             [3] zero.
+                             [3] TRSYL_FP32_REFINE: refinement sweeps that updated Y (the
+                             others stopped at refine_tol); otherwise zero.
                              trsyl_robust, trsyl_robust_adjoint and trsyl_robust_general
                              fill it (for
                              TRSYL_FP32_REFINE: the counts of the first, FP32-update solve);
@@ -178,7 +182,8 @@ int trsyl_bartels_stewart(int64_t m, int64_t n, const double *U, int64_t ldu, co
 
 /*
  * Batched adjoint solve: `count` independent problems A_i^T G_i + G_i B_i^T = alpha_i W_i (the
- * transposed problems of Sec. 8's gradient derivation), each reversed as in trsyl_robust_adjoint
+ * transposed problems whose solutions give the gradients of a loss <W, Y>, an extension beyond the
+ * paper), each reversed as in trsyl_robust_adjoint
  * and all solved by one batched forward solve (trsyl_robust_batched).  Arguments as in
  * trsyl_robust_batched, with W (in: W_i, out: G_i) in place of C; workspace >=
  * trsyl_adjoint_batched_workspace_size(count, m, n, tiles, opts).  A problem's results are

@@ -188,7 +188,8 @@ def sync_result(e, scale, info, stream=None) -> tuple[int, float, int]:
 def solve(A, B, C, *, counters=False, **kw):
     """Robust solve; returns (Y (m x n, column-major view), e (alpha = 2^-e), info), and with
     counters=True also the scaling-event counts {"fallback_solves" (element-level Algorithm 2),
-    "scaled_updates", "scaled_solves" (leaf-tiled robust tile solves)}."""
+    "scaled_updates", "scaled_solves" (leaf-tiled robust tile solves), "refine_sweeps" (sweeps of
+    the precision form that updated Y)}."""
     opts = make_opts(**kw)
     cnt = None
     if counters:
@@ -200,7 +201,8 @@ def solve(A, B, C, *, counters=False, **kw):
     out = (Yc.t(), int(e.item()), int(info.item()))
     if counters:
         c = cnt.cpu().tolist()
-        out = out + ({"fallback_solves": c[0], "scaled_updates": c[1], "scaled_solves": c[2]},)
+        out = out + ({"fallback_solves": c[0], "scaled_updates": c[1], "scaled_solves": c[2],
+                      "refine_sweeps": c[3]},)
     return out
 
 

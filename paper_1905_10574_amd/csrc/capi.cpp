@@ -273,7 +273,7 @@ namespace {
 int solve_core(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
                double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
                const Resolved &r0, int extra_flags, char *ws, hipEvent_t *ev, uint64_t *trace,
-               hipStream_t stream)
+               hipStream_t stream, const int32_t *skip = nullptr)
 {
     Resolved r = r0;
     r.flags |= extra_flags;
@@ -283,6 +283,7 @@ int solve_core(int64_t m, int64_t n, const double *A, int64_t lda, const double 
     P.scale_out = scale;
     P.info_out = info;
     P.trace = trace;
+    P.skip = skip;
     if (m == 0 || n == 0) {
         P.pt = P.qt = 0;
         if (launch_fill_zero(ws, kAlign, stream) != hipSuccess) return -100;
@@ -320,12 +321,15 @@ size_t refine_extra(int64_t m, int64_t n)
 }
 
 // Precision form: the tiled solve with FP32-MFMA tile updates (tile solves, bounds and scale
-// decisions in FP64), then max_sweeps refinement sweeps in FP64.  Sweep: with 2^sy > max|Y|,
+// decisions in FP64), then at most max_sweeps refinement sweeps in FP64.  Sweep: with 2^sy > max|Y|,
 //   R' = 2^-(e+sy) C0 - 2^-sy (A Y + Y B)            (FP64 MFMA GEMMs, C0 the original C)
+//   if eq. (9) of (Y, e), formed from ||R'||, ||A||, ||B||, ||Ys||, ||C0||, is at most refine_tol:
+//       stop (a device flag turns this and every later kernel of the refinement into a no-op)
 //   A D + D B = 2^-eD R'                              (the FP32-update solve, robust)
 //   Y <- 2^-(eD+x) Y + 2^(sy-x) D,  e <- e + eD + x  (so A Y + Y B = 2^-e C0 again; the extra
 //                                                      power of two x keeps Y in range)
-// All on the stream; no host synchronisation.
+// All on the stream; no host synchronisation.  counters[3] receives the number of sweeps that
+// updated Y.
 int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
                   double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
                   const Resolved &r, char *ws, hipEvent_t *ev, hipStream_t stream)
@@ -343,10 +347,13 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
     int64_t *eD = (int64_t *)(sc + 0);
     int64_t *negsy = (int64_t *)(sc + 8);
     int32_t *infoD = (int32_t *)(sc + 16);
-    int32_t *sy = (int32_t *)(sc + 20);
-    double *tY = (double *)(sc + 24);
-    int32_t *sD = (int32_t *)(sc + 32);
+    int32_t *sD = (int32_t *)(sc + 20);
+    int32_t *skip = (int32_t *)(sc + 24);
+    uint32_t *sweeps = (uint32_t *)(sc + 28);
+    int32_t *s5 = (int32_t *)(sc + 32);        // norm exponents of R', A, B, Y, C0
+    double *t5 = (double *)(sc + 56);          // and their sums of squares
     const int mi = (int)m, ni = (int)n;
+    if (launch_fill_zero(sc, kAlign, stream) != hipSuccess) return -100;
     if (hipMemcpy2DAsync(C0, 8 * (size_t)m, C, 8 * (size_t)ldc, 8 * (size_t)m, (size_t)n,
                          hipMemcpyDeviceToDevice, stream) != hipSuccess)
         return -100;
@@ -354,9 +361,14 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
     int rcode = solve_core(m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, rc, kFlagF32Updates, ws,
                            nullptr, nullptr, stream);
     if (rcode) return rcode;
+    if (r.max_sweeps > 0) {
+        if (launch_norm(A, lda, mi, mi, 1, part, s5 + 1, t5 + 1, stream) != hipSuccess) return -100;
+        if (launch_norm(B, ldb, ni, ni, 1, part, s5 + 2, t5 + 2, stream) != hipSuccess) return -100;
+        if (launch_norm(C0, mi, mi, ni, 0, part, s5 + 4, t5 + 4, stream) != hipSuccess) return -100;
+    }
     for (int sweep = 0; sweep < r.max_sweeps; ++sweep) {
-        if (launch_norm(C, ldc, mi, ni, 0, part, sy, tY, stream) != hipSuccess) return -100;
-        if (launch_neg_exp(sy, negsy, stream) != hipSuccess) return -100;
+        if (launch_norm(C, ldc, mi, ni, 0, part, s5 + 3, t5 + 3, stream, skip) != hipSuccess) return -100;
+        if (launch_neg_exp(s5 + 3, negsy, stream, skip) != hipSuccess) return -100;
         GemmDesc g{};
         g.M = mi; g.N = ni; g.K = mi;                 // D = 2^(-e-sy) C0 - 2^-sy A Y
         g.A = A; g.sAm = 1; g.sAk = lda; g.triA = 1;
@@ -368,6 +380,7 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
         g.csign = 1.0; g.ce0 = 0; g.ce1 = 1; g.ce2 = -1;
         g.ep1 = negsy; g.ep2 = scale_log2;
         g.mask = 0; g.pat = nullptr; g.ldpat = 1;
+        g.skip = skip;
         if (launch_gemm(g, stream) != hipSuccess) return -100;
         g.K = ni;                                     // D -= 2^-sy Y B
         g.A = C; g.sAm = 1; g.sAk = ldc; g.triA = 0;
@@ -376,15 +389,20 @@ int solve_refined(int64_t m, int64_t n, const double *A, int64_t lda, const doub
         g.Cin = D; g.ldcin = mi;
         g.ce1 = 0; g.ce2 = 0;
         if (launch_gemm(g, stream) != hipSuccess) return -100;
+        if (launch_norm(D, mi, mi, ni, 0, part, s5 + 0, t5 + 0, stream, skip) != hipSuccess) return -100;
+        if (launch_refine_check(s5, t5, scale_log2, r.refine_tol, skip, stream) != hipSuccess) return -100;
         rcode = solve_core(m, n, A, lda, B, ldb, D, m, eD, nullptr, infoD, rsweep, kFlagF32Updates, ws, nullptr,
-                           nullptr, stream);
+                           nullptr, stream, skip);
         if (rcode) return rcode;
-        if (launch_absmax_exp(D, m, mi, ni, part, sD, stream) != hipSuccess) return -100;
+        if (launch_absmax_exp(D, m, mi, ni, part, sD, stream, skip) != hipSuccess) return -100;
         if (launch_refine_update(C, ldc, D, m, mi, ni, eD, negsy, sD, scale_log2, info, infoD, scale,
-                                 stream) != hipSuccess)
+                                 stream, skip, sweeps) != hipSuccess)
             return -100;
     }
     if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return -100;
+    if (r.counters && hipMemcpyAsync(r.counters + 3, sweeps, sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                     stream) != hipSuccess)
+        return -100;
     return 0;
 }
 
@@ -406,8 +424,9 @@ struct BLayout {
     // column-major; then shared norm partials and per-problem sweep scalars
     bool refine = false;
     int max_sweeps = 0;
+    double refine_tol = 0.0;
     std::vector<size_t> c0, d;
-    size_t part = 0, eD = 0, negsy = 0, infoD = 0, sy = 0, tY = 0, sD = 0;
+    size_t part = 0, eD = 0, negsy = 0, infoD = 0, s5 = 0, t5 = 0, sD = 0, skip = 0;
 };
 
 // Returns 0 or the negative argument index that is invalid.
@@ -422,6 +441,7 @@ int make_blayout(int32_t count, const int64_t *m, const int64_t *n, const int32_
     if (int e = resolve(opts, &base, 14)) return e;
     B->refine = base.precision == TRSYL_FP32_REFINE;
     B->max_sweeps = base.max_sweeps;
+    B->refine_tol = base.refine_tol;
     B->workers = base.workers ? base.workers : device_cus();
     size_t o = 0;
     B->plans = o; o = align_up(o + sizeof(Plan) * (size_t)count);
@@ -460,9 +480,10 @@ int make_blayout(int32_t count, const int64_t *m, const int64_t *n, const int32_
         B->eD = o; o = align_up(o + 8 * (size_t)count);
         B->negsy = o; o = align_up(o + 8 * (size_t)count);
         B->infoD = o; o = align_up(o + 4 * (size_t)count);
-        B->sy = o; o = align_up(o + 4 * (size_t)count);
-        B->tY = o; o = align_up(o + 8 * (size_t)count);
+        B->s5 = o; o = align_up(o + 4 * 5 * (size_t)count);     // norm exponents: R', A, B, Y, C0
+        B->t5 = o; o = align_up(o + 8 * 5 * (size_t)count);     // and sums of squares
         B->sD = o; o = align_up(o + 4 * (size_t)count);
+        B->skip = o; o = align_up(o + 4 * (size_t)count);       // converged problems
     }
     B->total = o;
     return 0;
@@ -528,7 +549,7 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
 int batched_core(const BLayout &BL, int32_t count, const int64_t *m, const int64_t *n, const double *const *A,
                  const int64_t *lda, const double *const *B, const int64_t *ldb, double *const *C,
                  const int64_t *ldc, int64_t *scale_log2, double *scale, int32_t *info, int extra_flags,
-                 char *ws, hipEvent_t *ev, hipStream_t stream)
+                 char *ws, hipEvent_t *ev, hipStream_t stream, const int32_t *skip = nullptr)
 {
     // host images of the plans and the stage offset tables
     std::vector<Plan> plans(count);
@@ -548,6 +569,7 @@ int batched_core(const BLayout &BL, int32_t count, const int64_t *m, const int64
         P.scale_out = scale ? scale + p : nullptr;
         P.info_out = info + p;
         P.trace = nullptr;
+        P.skip = skip ? skip + p : nullptr;
         plans[p] = P;
         const int64_t items = std::max(m[p], n[p]) + 2;
         const int gS = (L.pt && L.qt) ? (int)std::min<int64_t>((items + 255) / 256, 64) : 0;
@@ -621,14 +643,29 @@ int batched_refined(const BLayout &BL, int32_t count, const int64_t *m, const in
     if (rcode) return rcode;
     double *part = (double *)(ws + BL.part);
     int64_t *eD = (int64_t *)(ws + BL.eD), *negsy = (int64_t *)(ws + BL.negsy);
-    int32_t *infoD = (int32_t *)(ws + BL.infoD), *sy = (int32_t *)(ws + BL.sy), *sD = (int32_t *)(ws + BL.sD);
-    double *tY = (double *)(ws + BL.tY);
+    int32_t *infoD = (int32_t *)(ws + BL.infoD), *s5 = (int32_t *)(ws + BL.s5), *sD = (int32_t *)(ws + BL.sD);
+    double *t5 = (double *)(ws + BL.t5);
+    int32_t *skip = (int32_t *)(ws + BL.skip);
+    if (launch_fill_zero(skip, 4 * (size_t)count, stream) != hipSuccess) return -100;
+    if (BL.max_sweeps > 0) {
+        for (int p = 0; p < count; ++p) {
+            if (m[p] == 0 || n[p] == 0) continue;
+            const int mi = (int)m[p], ni = (int)n[p];
+            if (launch_norm(A[p], lda[p], mi, mi, 1, part, s5 + 5 * p + 1, t5 + 5 * p + 1, stream) != hipSuccess ||
+                launch_norm(B[p], ldb[p], ni, ni, 1, part, s5 + 5 * p + 2, t5 + 5 * p + 2, stream) != hipSuccess ||
+                launch_norm((const double *)(ws + BL.c0[p]), mi, mi, ni, 0, part, s5 + 5 * p + 4, t5 + 5 * p + 4,
+                            stream) != hipSuccess)
+                return -100;
+        }
+    }
     for (int sweep = 0; sweep < BL.max_sweeps; ++sweep) {
         for (int p = 0; p < count; ++p) {
             if (m[p] == 0 || n[p] == 0) continue;
             const int mi = (int)m[p], ni = (int)n[p];
-            if (launch_norm(C[p], ldc[p], mi, ni, 0, part, sy + p, tY + p, stream) != hipSuccess) return -100;
-            if (launch_neg_exp(sy + p, negsy + p, stream) != hipSuccess) return -100;
+            const int32_t *sk = skip + p;
+            if (launch_norm(C[p], ldc[p], mi, ni, 0, part, s5 + 5 * p + 3, t5 + 5 * p + 3, stream, sk) != hipSuccess)
+                return -100;
+            if (launch_neg_exp(s5 + 5 * p + 3, negsy + p, stream, sk) != hipSuccess) return -100;
             GemmDesc g{};
             g.M = mi; g.N = ni; g.K = mi;                 // D = 2^(-e-sy) C0 - 2^-sy A Y
             g.A = A[p]; g.sAm = 1; g.sAk = lda[p]; g.triA = 1;
@@ -640,6 +677,7 @@ int batched_refined(const BLayout &BL, int32_t count, const int64_t *m, const in
             g.csign = 1.0; g.ce0 = 0; g.ce1 = 1; g.ce2 = -1;
             g.ep1 = negsy + p; g.ep2 = scale_log2 + p;
             g.mask = 0; g.pat = nullptr; g.ldpat = 1;
+            g.skip = sk;
             if (launch_gemm(g, stream) != hipSuccess) return -100;
             g.K = ni;                                     // D -= 2^-sy Y B
             g.A = C[p]; g.sAm = 1; g.sAk = ldc[p]; g.triA = 0;
@@ -648,16 +686,21 @@ int batched_refined(const BLayout &BL, int32_t count, const int64_t *m, const in
             g.Cin = Dp[p]; g.ldcin = mi;
             g.ce1 = 0; g.ce2 = 0;
             if (launch_gemm(g, stream) != hipSuccess) return -100;
+            if (launch_norm(Dp[p], mi, mi, ni, 0, part, s5 + 5 * p + 0, t5 + 5 * p + 0, stream, sk) != hipSuccess)
+                return -100;
+            if (launch_refine_check(s5 + 5 * p, t5 + 5 * p, scale_log2 + p, BL.refine_tol, skip + p, stream) !=
+                hipSuccess)
+                return -100;
         }
         rcode = batched_core(BL, count, m, n, A, lda, B, ldb, Dp.data(), ldd.data(), eD, nullptr, infoD,
-                             kFlagF32Updates, ws, nullptr, stream);
+                             kFlagF32Updates, ws, nullptr, stream, skip);
         if (rcode) return rcode;
         for (int p = 0; p < count; ++p) {
             if (m[p] == 0 || n[p] == 0) continue;
             const int mi = (int)m[p], ni = (int)n[p];
-            if (launch_absmax_exp(Dp[p], mi, mi, ni, part, sD + p, stream) != hipSuccess) return -100;
+            if (launch_absmax_exp(Dp[p], mi, mi, ni, part, sD + p, stream, skip + p) != hipSuccess) return -100;
             if (launch_refine_update(C[p], ldc[p], Dp[p], mi, mi, ni, eD + p, negsy + p, sD + p, scale_log2 + p,
-                                     info + p, infoD + p, scale ? scale + p : nullptr, stream) != hipSuccess)
+                                     info + p, infoD + p, scale ? scale + p : nullptr, stream, skip + p) != hipSuccess)
                 return -100;
         }
     }

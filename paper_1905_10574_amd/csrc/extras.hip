@@ -110,6 +110,7 @@ struct GemmLds {
 __global__ void __launch_bounds__(512) k_gemm(GemmDesc g)
 {
     __shared__ GemmLds L;
+    if (g.skip && __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)g.skip) != 0) return;
     const int m0 = kGT * blockIdx.x, n0 = kGT * blockIdx.y;
     const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
@@ -244,9 +245,10 @@ __device__ __forceinline__ double block_max(double v, double *red)
 // pass 0: partial max |x|;  pass 1: partial sum of (x 2^-s)^2 with 2^s the power of two at or
 // above the max (s read from *sexp).
 __global__ void k_norm_part(const double *X, int64_t ld, int rows, int cols, int pattern, int pass,
-                            const int32_t *sexp, double *part)
+                            const int32_t *sexp, double *part, const int32_t *skip)
 {
     __shared__ double red[16];
+    if (skip && __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)skip) != 0) return;
     const int64_t tot = (int64_t)rows * cols;
     const int s = pass ? *sexp : 0;
     double v = 0.0;
@@ -265,9 +267,11 @@ __global__ void k_norm_part(const double *X, int64_t ld, int rows, int cols, int
 // Reduces nparts partials in order.  pass 0: *sexp = the exponent s with 2^s >= max (0 for a
 // zero matrix) and a non-finite max is flagged by s = INT32_MAX.  pass 1: out[0] = sum, so the
 // norm is 2^s sqrt(out[0]).
-__global__ void k_norm_final(const double *part, int nparts, int pass, int32_t *sexp, double *out)
+__global__ void k_norm_final(const double *part, int nparts, int pass, int32_t *sexp, double *out,
+                             const int32_t *skip)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (skip && *skip) return;
     if (pass == 0) {
         double m = 0.0;
         bool bad = false;
@@ -293,11 +297,10 @@ __global__ void k_norm_final(const double *part, int nparts, int pass, int32_t *
 // the Y, C scales described in trsyl_residual: Y is used as Ys = 2^-sy Y and alpha C as
 // 2^-(e + sy) C.
 // ---------------------------------------------------------------------------------------------
-__global__ void k_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out)
+__device__ double residual_quotient(const int32_t *s5, const double *t5, const int64_t *e)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     for (int i = 0; i < 5; ++i)
-        if (s5[i] == 0x7FFFFFFF || !(t5[i] <= 1.7976931348623157e308)) { *out = __builtin_nan(""); return; }
+        if (s5[i] == 0x7FFFFFFF || !(t5[i] <= 1.7976931348623157e308)) return __builtin_nan("");
     // norms as (mantissa, exponent): R, A, B, Ys, aC
     const int sy = s5[3];
     double v[5];
@@ -314,11 +317,25 @@ __global__ void k_residual_final(const int32_t *s5, const double *t5, const int6
     const int64_t xd = xp > x[4] ? xp : x[4];
     const double d = ldexp(p, (int)(xp - xd > -3000 ? xp - xd : -3000)) +
                      ldexp(v[4], (int)(x[4] - xd > -3000 ? x[4] - xd : -3000));
-    if (d == 0.0) { *out = v[0] == 0.0 ? 0.0 : __builtin_inf(); return; }
+    if (d == 0.0) return v[0] == 0.0 ? 0.0 : __builtin_inf();
     int64_t xq = x[0] - xd;
     if (xq > 3000) xq = 3000;
     if (xq < -3000) xq = -3000;
-    *out = ldexp(v[0] / d, (int)xq);
+    return ldexp(v[0] / d, (int)xq);
+}
+
+__global__ void k_residual_final(const int32_t *s5, const double *t5, const int64_t *e, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    *out = residual_quotient(s5, t5, e);
+}
+
+__global__ void k_refine_check(const int32_t *s5, const double *t5, const int64_t *e, double tol, int32_t *skip)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (*skip) return;
+    const double q = residual_quotient(s5, t5, e);
+    if (q <= tol) *skip = 1;
 }
 
 // dC = 2^(eG - eY) G
@@ -335,8 +352,9 @@ __global__ void k_scale_copy(const double *G, int64_t ldg_, int m, int n, const 
 }
 
 // -sy with 2^sy >= max|Y| as an int64 (the norm pass-0 exponent of Y)
-__global__ void k_neg_exp(const int32_t *s, int64_t *out)
+__global__ void k_neg_exp(const int32_t *s, int64_t *out, const int32_t *skip)
 {
+    if (skip && *skip) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = -(int64_t)(*s == 0x7FFFFFFF ? 0 : *s);
 }
 
@@ -350,8 +368,10 @@ __global__ void k_neg_exp(const int32_t *s, int64_t *out)
 // ---------------------------------------------------------------------------------------------
 __global__ void k_refine_update(double *Y, int64_t ldy, const double *D, int64_t ldd, int m, int n,
                                 const int64_t *eD, const int64_t *negsy, const int32_t *sD, int64_t *e,
-                                int32_t *info, const int32_t *infoD, double *scale)
+                                int32_t *info, const int32_t *infoD, double *scale, const int32_t *skip,
+                                uint32_t *sweeps)
 {
+    if (skip && __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)skip) != 0) return;
     const int64_t sy = -*negsy;
     const int64_t sd = *sD == 0x7FFFFFFF ? 0 : *sD;
     int64_t top = sy - *eD;
@@ -374,6 +394,7 @@ __global__ void k_refine_update(double *Y, int64_t ldy, const double *D, int64_t
         *e = en;
         if (*infoD > *info) *info = *infoD;
         if (scale) *scale = en > 1074 ? 0.0 : ldexp(1.0, -(int)en);
+        if (sweeps) *sweeps += 1u;
     }
 }
 
@@ -447,19 +468,26 @@ hipError_t launch_scale_copy(const double *G, int64_t ldg_, int m, int n, const 
 
 // 2^s sqrt(*t) = ||X||_F (pattern 1: quasi-triangular part).  part: kNormParts doubles.
 hipError_t launch_norm(const double *X, int64_t ld, int rows, int cols, int pattern, double *part,
-                       int32_t *s, double *t, hipStream_t st)
+                       int32_t *s, double *t, hipStream_t st, const int32_t *skip)
 {
     const int nb = kNormParts;
-    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(512), 0, st, X, ld, rows, cols, pattern, 0, s, part);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, nb, 0, s, t);
-    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(512), 0, st, X, ld, rows, cols, pattern, 1, s, part);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, nb, 1, s, t);
+    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(512), 0, st, X, ld, rows, cols, pattern, 0, s, part, skip);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, nb, 0, s, t, skip);
+    hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(512), 0, st, X, ld, rows, cols, pattern, 1, s, part, skip);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, nb, 1, s, t, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st)
+hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st, const int32_t *skip)
 {
-    hipLaunchKernelGGL(k_neg_exp, dim3(1), dim3(64), 0, st, s, out);
+    hipLaunchKernelGGL(k_neg_exp, dim3(1), dim3(64), 0, st, s, out, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_check(const int32_t *s5, const double *t5, const int64_t *e, double tol, int32_t *skip,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(64), 0, st, s5, t5, e, tol, skip);
     return hipGetLastError();
 }
 
@@ -472,19 +500,20 @@ hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int6
 
 hipError_t launch_refine_update(double *Y, int64_t ldy, const double *D, int64_t ldd, int m, int n,
                                 const int64_t *eD, const int64_t *negsy, const int32_t *sD, int64_t *e,
-                                int32_t *info, const int32_t *infoD, double *scale, hipStream_t st)
+                                int32_t *info, const int32_t *infoD, double *scale, hipStream_t st,
+                                const int32_t *skip, uint32_t *sweeps)
 {
     hipLaunchKernelGGL(k_refine_update, dim3(grid_for((int64_t)m * n)), dim3(256), 0, st, Y, ldy, D, ldd,
-                       m, n, eD, negsy, sD, e, info, infoD, scale);
+                       m, n, eD, negsy, sD, e, info, infoD, scale, skip, sweeps);
     return hipGetLastError();
 }
 
 // 2^s > max |X| (s = 0 for a zero matrix, INT32_MAX if non-finite).  part: kNormParts doubles.
 hipError_t launch_absmax_exp(const double *X, int64_t ld, int rows, int cols, double *part, int32_t *s,
-                             hipStream_t st)
+                             hipStream_t st, const int32_t *skip)
 {
-    hipLaunchKernelGGL(k_norm_part, dim3(kNormParts), dim3(512), 0, st, X, ld, rows, cols, 0, 0, s, part);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, kNormParts, 0, s, (double *)nullptr);
+    hipLaunchKernelGGL(k_norm_part, dim3(kNormParts), dim3(512), 0, st, X, ld, rows, cols, 0, 0, s, part, skip);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, part, kNormParts, 0, s, (double *)nullptr, skip);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct GemmDesc {
     int mask;
     const double *pat;
     int64_t ldpat;
+    const int32_t *skip;     // optional: when *skip != 0 the kernel does nothing
 };
 
 hipError_t launch_quasi_copy(const double *T, int64_t ldt, int n, bool flip, double sign, double *D,
@@ -49,8 +50,8 @@ hipError_t launch_gemm(const GemmDesc &g, hipStream_t s);
 hipError_t launch_scale_copy(const double *G, int64_t ldg_, int m, int n, const int64_t *eG,
                              const int64_t *eY, double *dC, int64_t lddc, hipStream_t s);
 hipError_t launch_norm(const double *X, int64_t ld, int rows, int cols, int pattern, double *part,
-                       int32_t *s, double *t, hipStream_t st);
-hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st);
+                       int32_t *s, double *t, hipStream_t st, const int32_t *skip = nullptr);
+hipError_t launch_neg_exp(const int32_t *s, int64_t *out, hipStream_t st, const int32_t *skip = nullptr);
 hipError_t launch_norm_shift(const int32_t *s, const double *t, int64_t *negshift, int64_t *total,
                              hipStream_t st);
 hipError_t launch_add_exponent(int64_t *e, double *scale, const int64_t *add, hipStream_t st);
@@ -59,8 +60,15 @@ hipError_t launch_residual_final(const int32_t *s5, const double *t5, const int6
 
 hipError_t launch_refine_update(double *Y, int64_t ldy, const double *D, int64_t ldd, int m, int n,
                                 const int64_t *eD, const int64_t *negsy, const int32_t *sD, int64_t *e,
-                                int32_t *info, const int32_t *infoD, double *scale, hipStream_t st);
+                                int32_t *info, const int32_t *infoD, double *scale, hipStream_t st,
+                                const int32_t *skip = nullptr, uint32_t *sweeps = nullptr);
 hipError_t launch_absmax_exp(const double *X, int64_t ld, int rows, int cols, double *part, int32_t *s,
-                             hipStream_t st);
+                             hipStream_t st, const int32_t *skip = nullptr);
+// Convergence test of the precision form's sweeps: eq. (9) of the current iterate from the five
+// norm pairs (as for trsyl_residual: R' of the scaled iterate, A, B, Ys, C); when it is at most
+// tol, *skip is set (and stays set), which turns every later kernel of the refinement into a
+// no-op.
+hipError_t launch_refine_check(const int32_t *s5, const double *t5, const int64_t *e, double tol, int32_t *skip,
+                               hipStream_t st);
 
 }  // namespace trsyl

@@ -68,6 +68,8 @@ struct Plan {
     int32_t *info_out;
     uint64_t spin_limit;    // watchdog for dependency waits
     uint64_t *trace;        // optional per-task timing records (4 words per task)
+    const int32_t *skip;    // optional: when *skip != 0 every kernel of the solve returns at once
+                            // (refinement sweeps after convergence)
 };
 
 // A copy of the plan whose every field is read with readfirstlane.  The plan reaches kernels and
@@ -100,7 +102,14 @@ __device__ __forceinline__ Plan uniform_plan(const Plan &in)
     P.e_out = uniptr(in.e_out); P.scale_out = uniptr(in.scale_out); P.info_out = uniptr(in.info_out);
     P.spin_limit = (uint64_t)uni64((int64_t)in.spin_limit);
     P.trace = uniptr(in.trace);
+    P.skip = uniptr(in.skip);
     return P;
+}
+
+// The solve was switched off by its skip flag (read by every kernel of the solve on entry).
+__device__ __forceinline__ bool plan_skipped(const Plan &P)
+{
+    return P.skip && __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)P.skip) != 0;
 }
 
 // blocks per tile of the consistency pass

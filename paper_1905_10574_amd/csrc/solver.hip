@@ -22,6 +22,7 @@ namespace trsyl {
 // ---------------------------------------------------------------------------------------------
 __device__ void structure_body(const Plan &P, int64_t blk, int64_t nblk)
 {
+    if (plan_skipped(P)) return;
     const int64_t tid = blk * blockDim.x + threadIdx.x;
     const int64_t nthr = nblk * blockDim.x;
     for (int64_t i = tid; i + 2 < P.m; i += nthr)
@@ -98,12 +99,14 @@ __device__ void bound_tile(const Plan &P, const double *T, int64_t ld, const int
 
 __device__ void bounds_A_body(const Plan &P, int b)
 {
+    if (plan_skipped(P)) return;
     const int i = b / P.pt, k = b % P.pt;
     if (i > k) return;
     bound_tile(P, P.A, P.lda, P.rowoff, P.pt, i, k, P.anorm, nullptr);
 }
 __device__ void bounds_B_body(const Plan &P, int b)
 {
+    if (plan_skipped(P)) return;
     const int l = b / P.qt, j = b % P.qt;
     if (l > j) return;
     bound_tile(P, P.B, P.ldb, P.coloff, P.qt, l, j, P.bnorm, P.bdiag1);
@@ -114,6 +117,7 @@ __global__ void __launch_bounds__(kThreads) k_bounds_B(Plan P) { bounds_B_body(P
 // ||C_kl||_inf, input check, and version 0 of every tile's state.
 __device__ void bounds_C_body(const Plan &P, int T)
 {
+    if (plan_skipped(P)) return;
     __shared__ double red[kWaves];
     const int k = T / P.qt, l = T % P.qt;
     const int r0 = P.rowoff[k], r1 = P.rowoff[k + 1], c0 = P.coloff[l], c1 = P.coloff[l + 1];
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
     __shared__ TaskLds L;
     __shared__ uint32_t s_ticket;
     __shared__ int s_ok;
-    if (uniform(*(volatile int32_t *)P.status) >= kBadStructure) return;
+    if (plan_skipped(P) || uniform(*(volatile int32_t *)P.status) >= kBadStructure) return;
     double *scratch = P.scratch + (size_t)blockIdx.x * kMaxTile * kMaxTile;
     const uint32_t slabs = (uint32_t)P.slabs;
     const uint32_t ntasks = (uint32_t)P.ntasks;
@@ -229,7 +233,7 @@ __global__ void __launch_bounds__(kThreads) k_front_solve(Plan Pk, int d)
 {
     const Plan P = uniform_plan(Pk);
     __shared__ SolveLds L;
-    if (*(volatile int32_t *)P.status >= kBadStructure) return;
+    if (plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure) return;
     const int lmin = d - (P.pt - 1) > 0 ? d - (P.pt - 1) : 0;
     const int l = lmin + blockIdx.x;
     const int k = P.pt - 1 - (d - l);
@@ -244,7 +248,7 @@ __global__ void __launch_bounds__(kThreads) k_front_update(Plan Pk, int d, int k
 {
     const Plan P = uniform_plan(Pk);
     __shared__ UpdateLds L;
-    if (*(volatile int32_t *)P.status >= kBadStructure) return;
+    if (plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure) return;
     const int lmin = d - (P.pt - 1) > 0 ? d - (P.pt - 1) : 0;
     const int ntgt = (kind == kTaskColUpdate) ? P.pt - 1 : P.qt - 1;
     const int slab = blockIdx.x % P.slabs;
@@ -272,6 +276,7 @@ __global__ void __launch_bounds__(kThreads) k_front_update(Plan Pk, int d, int k
 // ---------------------------------------------------------------------------------------------
 __device__ void finalize_body(const Plan &P)
 {
+    if (plan_skipped(P)) return;
     __shared__ int red[kWaves];
     int e = 0;
     for (int T = threadIdx.x; T < P.pt * P.qt; T += kThreads)
@@ -294,6 +299,7 @@ __global__ void __launch_bounds__(kThreads) k_finalize(Plan P) { finalize_body(P
 
 __device__ void consistency_body(const Plan &P, int per_tile, int b)
 {
+    if (plan_skipped(P)) return;
     const int T = b / per_tile, part = b % per_tile;
     const int st = *(volatile int32_t *)P.status;
     if (st >= kBadStructure) return;
@@ -396,7 +402,7 @@ __global__ void __launch_bounds__(kThreads) k_dag_b(const Plan *plans, const uin
         const uint32_t slabs = (uint32_t)P.slabs;
         const int kind = uniform(task_kind(task)), T = uniform(task_T(task));
         if (threadIdx.x == 0) {
-            const bool bad = *(volatile int32_t *)P.status >= kBadStructure;
+            const bool bad = plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure;
             bool ok = true;
             if (!bad) {
                 const uint64_t t0 = wall_clock64();

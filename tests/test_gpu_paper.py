@@ -1,4 +1,4 @@
-"""GPU tests on the test matrices of the paper's experiments (Sec. 4): C and the strict upper
+"""GPU tests on the test matrices (Sec. 3) of the paper's experiments (Sec. 4): C and the strict upper
 parts of A and B are ones, the diagonal blocks are mu T and nu T with T = [1] or
 [[1, 1], [-1, 1]].  mu and nu control the growth of the substitution:
 
@@ -58,7 +58,7 @@ def test_paper_no_scaling(T, orc):
     Y, e, info, cnt = T.solve(A, B, C, tile=64, counters=True)
     Y = Y.cpu().numpy()
     assert info == 0 and e == 0
-    assert cnt == {"fallback_solves": 0, "scaled_updates": 0, "scaled_solves": 0}
+    assert cnt == {"fallback_solves": 0, "scaled_updates": 0, "scaled_solves": 0, "refine_sweeps": 0}
     Yo, eo, _ = orc.drsylv(A, B, C, 64)
     assert eo == 0
     assert _rel(Y, Yo) <= 1e-10
@@ -78,7 +78,7 @@ def test_paper_cost_of_robustness(T, orc, mu):
     Yo, eo, _ = orc.drsylv(A, B, C, 64)
     if mu >= 10.0:
         assert e == 0 and eo == 0
-        assert cnt == {"fallback_solves": 0, "scaled_updates": 0, "scaled_solves": 0}
+        assert cnt == {"fallback_solves": 0, "scaled_updates": 0, "scaled_solves": 0, "refine_sweeps": 0}
         assert _rel(Y, Yo) <= 1e-10
     else:
         # every tile needs scaling inside; the leaf-tiled robust solve handles all of them
@@ -97,4 +97,4 @@ def test_counters_empty(T):
     C = np.zeros((5, 0))
     Y, e, info, cnt = T.solve(A, B, C, counters=True)
     assert e == 0 and info == 0
-    assert cnt == {"fallback_solves": 0, "scaled_updates": 0, "scaled_solves": 0}
+    assert cnt == {"fallback_solves": 0, "scaled_updates": 0, "scaled_solves": 0, "refine_sweeps": 0}

@@ -32,6 +32,7 @@ def test_fp32_refine_separated(T, m, n, tile, sweeps):
     Y = Y.cpu().numpy()
     err = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
     assert err <= 1e-10, err
+    assert np.abs(Y - Yo).max() <= 1e-10 * np.abs(Yo).max()
 
 
 def test_fp32_refine_growth(T):
@@ -72,3 +73,24 @@ def test_fp32_refine_batched_matches_single(T):
             assert T.residual(A, B, Y, e, C) <= 1e-12
             if i == 3:
                 assert e > 0
+
+
+def test_refine_tol_stops_the_sweeps(T):
+    """refine_tol: every sweep starts with an eq. (9) check of the current iterate on the device and
+    the refinement stops once it is at most refine_tol.  A loose tolerance runs no sweep (the result
+    is the FP32-update solve's), a vanishing one runs all of them, and the default stops after the
+    sweeps it needs -- with exactly the result of running that many sweeps unconditionally."""
+    A, B, C = W.separated_problem(21, 300, 257)
+    kw = dict(tile=64, precision="fp32_refine", counters=True)
+    Y0, e0, i0 = T.solve(A, B, C, max_sweeps=-1, **kw)[:3]
+    Yl, el, il, cl = T.solve(A, B, C, max_sweeps=3, refine_tol=1.0, **kw)
+    assert cl["refine_sweeps"] == 0 and torch.equal(Yl.cpu(), Y0.cpu())
+    Ya, ea, ia, ca = T.solve(A, B, C, max_sweeps=3, refine_tol=1e-300, **kw)
+    assert ca["refine_sweeps"] == 3
+    Yd, ed, idd, cd = T.solve(A, B, C, max_sweeps=3, **kw)
+    k = cd["refine_sweeps"]
+    print(f"  default tolerance: {k} sweep(s)", flush=True)
+    assert 1 <= k < 3 and idd == 0
+    assert T.residual(A, B, Yd, ed, C) <= 1e-12
+    Yk, ek, ik, ck = T.solve(A, B, C, max_sweeps=k, refine_tol=1e-300, **kw)
+    assert ck["refine_sweeps"] == k and ek == ed and torch.equal(Yk.cpu(), Yd.cpu())
