@@ -116,6 +116,28 @@ int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const doubl
                  const trsyl_opts *opts, void *workspace, size_t ws_bytes, trsyl_stream_t stream);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation: trsyl_robust without a workspace argument.
+ *   - The solver state lives in a device array of TRSYL_NOALLOC_BYTES (64 MiB) that the library
+ *     holds on every GPU it runs on until the process ends; nothing is allocated or freed by the
+ *     call (the first call on a device only looks up that device's copy of the array).
+ *   - Arguments as for trsyl_robust, opts as well, except: precision must be TRSYL_FP64 (else -12),
+ *     the scheduler is always the per-front one (opts->scheduler and opts->workers are ignored) and
+ *     opts->trace is ignored.  Results are bit-identical to trsyl_robust's with the same tiles.
+ *   - The state grows with the tile counts: about 8 min(p_t, q_t) 257^2 bytes of per-workgroup tiles
+ *     plus small per-tile tables (m = n = 8192 with tile 128 uses ~34 MB).  A problem whose state
+ *     exceeds TRSYL_NOALLOC_BYTES is rejected with TRSYL_ENOSPACE before anything is enqueued.
+ *   - All calls on one GPU share the array and it keeps the last call's contents (each call clears
+ *     the state it reads): calls that overlap on one GPU -- from several host threads or on several
+ *     streams without ordering between them -- race and give undefined results.
+ */
+#define TRSYL_NOALLOC_BYTES (64u << 20)
+#define TRSYL_ENOSPACE (-201)
+int trsyl_robust_noalloc(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                         double *C, int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info,
+                         const trsyl_opts *opts, trsyl_stream_t stream);
+
+/*
  * Adjoint solve A^T G + G B^T = alpha W, used for gradients (L = <W, Y> gives dL/dC = alpha_Y G,
  * dL/dA = -G Y^T on A's pattern, dL/dB = -Y^T G).  Same arguments as trsyl_robust with W in C.
  * The transposed problem is mapped onto the forward one by order reversal:

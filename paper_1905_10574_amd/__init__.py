@@ -55,6 +55,9 @@ def lib() -> ctypes.CDLL:
         L.trsyl_robust.argtypes = [_I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _P,
                                    ctypes.POINTER(Opts), _P, ctypes.c_size_t, _P]
         L.trsyl_robust.restype = ctypes.c_int
+        L.trsyl_robust_noalloc.argtypes = [_I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _P,
+                                           ctypes.POINTER(Opts), _P]
+        L.trsyl_robust_noalloc.restype = ctypes.c_int
         L.trsyl_adjoint_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(Opts)]
         L.trsyl_adjoint_workspace_size.restype = ctypes.c_size_t
         L.trsyl_robust_adjoint.argtypes = L.trsyl_robust.argtypes
@@ -171,6 +174,32 @@ def solve_async(A, B, C, opts: Opts | None = None, *, workspace=None):
     if rc != 0:
         raise RuntimeError(f"trsyl_robust rejected its arguments: {rc}")
     solve_async._keep = (Ac, Bc, ws_keep)  # keep inputs alive until the caller synchronises
+    return Yc, e, sc, info
+
+
+NOALLOC_BYTES = 64 << 20      # TRSYL_NOALLOC_BYTES
+ENOSPACE = -201               # TRSYL_ENOSPACE
+
+
+def solve_noalloc_async(A, B, C, opts: Opts | None = None):
+    """Enqueue trsyl_robust_noalloc (the solve that allocates nothing on the device: its state lives
+    in the library's fixed per-GPU array) on the current stream.  Returns (Ys, e, scale, info) as
+    solve_async does; raises on a rejected call (TRSYL_ENOSPACE for a problem too large for it)."""
+    opts = opts or make_opts()
+    Ac = colmajor(A)
+    dev = Ac.device
+    Bc = colmajor(B, dev)
+    Yc = colmajor(C, dev, fresh=True)
+    m, n = Yc.shape[1], Yc.shape[0]
+    e = torch.zeros(1, dtype=torch.int64, device=dev)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    rc = lib().trsyl_robust_noalloc(m, n, Ac.data_ptr(), max(1, m), Bc.data_ptr(), max(1, n), Yc.data_ptr(),
+                                    max(1, m), e.data_ptr(), sc.data_ptr(), info.data_ptr(), ctypes.byref(opts),
+                                    _stream(dev))
+    if rc != 0:
+        raise RuntimeError(f"trsyl_robust_noalloc rejected the call: {rc}")
+    solve_noalloc_async._keep = (Ac, Bc)
     return Yc, e, sc, info
 
 

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrsyl.so")
 ARCH = os.environ.get("TRSYL_ARCH", "gfx950")
 
-HIP_SOURCES = ["solver.hip", "extras.hip"]
+HIP_SOURCES = ["solver.hip", "extras.hip", "noalloc.hip"]
 HOST_SOURCES = ["capi.cpp", "capi_extras.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 # packed FP32 VALU forms are disabled for all device code

@@ -710,6 +710,61 @@ int batched_refined(const BLayout &BL, int32_t count, const int64_t *m, const in
 
 }  // namespace
 
+namespace trsyl {
+
+// The solve of trsyl_robust_noalloc on a caller-provided region `ws` of `cap` bytes: FP64, the
+// per-front scheduler (no host-built task list), one scratch tile per workgroup of a front.
+// Returns 0, a negative argument index, kNoAllocTooLarge when the state does not fit in `cap`, or
+// -100 on a launch error.  Allocates nothing.
+static int noalloc_resolve(const trsyl_opts *opts, Resolved *r)
+{
+    if (int e = resolve(opts, r, 12)) return e;
+    if (r->precision != TRSYL_FP64) return -12;
+    r->scheduler = TRSYL_SCHED_FRONTS;
+    r->workers = 1;       // make_layout raises it to the widest front, the only workgroups that need a tile
+    return 0;
+}
+
+// Bytes of state the no-allocation solve needs (host only, no device call).
+int noalloc_need(int64_t m, int64_t n, const trsyl_opts *opts, size_t *need)
+{
+    Resolved r;
+    if (int e = noalloc_resolve(opts, &r)) return e;
+    *need = (m > 0 && n > 0) ? make_layout(m, n, r).total : kAlign;
+    return 0;
+}
+
+int noalloc_solve(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                  int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
+                  char *ws, size_t cap, hipStream_t stream)
+{
+    Resolved r;
+    if (int e = noalloc_resolve(opts, &r)) return e;
+    if (m > 0 && n > 0 && make_layout(m, n, r).total > cap) return kNoAllocTooLarge;
+    hipEvent_t *ev = opts ? (hipEvent_t *)opts->profile_events : nullptr;
+    return solve_core(m, n, A, lda, B, ldb, C, ldc, scale_log2, scale, info, r, 0, ws, ev, nullptr, stream);
+}
+
+// Argument checks shared by trsyl_robust and trsyl_robust_noalloc (workspace aside).
+int check_solve_args(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                     const double *C, int64_t ldc, const int64_t *scale_log2, const int32_t *info)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (m > 0 && bad_ptr(A)) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (n > 0 && bad_ptr(B)) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (m > 0 && n > 0 && bad_ptr(C)) return -7;
+    if (ldc < std::max<int64_t>(1, m)) return -8;
+    if (bad_ptr(scale_log2)) return -9;
+    if (bad_ptr(info)) return -11;
+    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
+    return 0;
+}
+
+}  // namespace trsyl
+
 extern "C" {
 
 void trsyl_default_opts(trsyl_opts *o)
@@ -741,19 +796,9 @@ int trsyl_robust(int64_t m, int64_t n, const double *A, int64_t lda, const doubl
                  const trsyl_opts *opts, void *workspace, size_t ws_bytes, trsyl_stream_t stream_)
 {
     hipStream_t stream = (hipStream_t)stream_;
-    if (m < 0) return -1;
-    if (n < 0) return -2;
-    if (m > 0 && bad_ptr(A)) return -3;
-    if (lda < std::max<int64_t>(1, m)) return -4;
-    if (n > 0 && bad_ptr(B)) return -5;
-    if (ldb < std::max<int64_t>(1, n)) return -6;
-    if (m > 0 && n > 0 && bad_ptr(C)) return -7;
-    if (ldc < std::max<int64_t>(1, m)) return -8;
-    if (bad_ptr(scale_log2)) return -9;
-    if (bad_ptr(info)) return -11;
+    if (int e = check_solve_args(m, n, A, lda, B, ldb, C, ldc, scale_log2, info)) return e;
     Resolved r;
     if (int e = resolve(opts, &r, 12)) return e;
-    if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return -1;
     if (bad_ptr(workspace) || ((uintptr_t)workspace % kAlign) != 0) return -13;
     const size_t need = trsyl_workspace_size(m, n, opts);
     if (ws_bytes < need) return -14;

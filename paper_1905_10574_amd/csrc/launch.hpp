@@ -29,4 +29,16 @@ struct BatchedLaunch {
 };
 hipError_t launch_batched(const BatchedLaunch &b, hipStream_t s);
 
+// trsyl_robust_noalloc's core (capi.cpp) and its size error.
+constexpr int kNoAllocTooLarge = -201;
+}  // namespace trsyl
+#include "../../include/trsyl.h"
+namespace trsyl {
+int noalloc_need(int64_t m, int64_t n, const trsyl_opts *opts, size_t *need);
+int noalloc_solve(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                  int64_t ldc, int64_t *scale_log2, double *scale, int32_t *info, const trsyl_opts *opts,
+                  char *ws, size_t cap, hipStream_t stream);
+int check_solve_args(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
+                     const double *C, int64_t ldc, const int64_t *scale_log2, const int32_t *info);
+
 }  // namespace trsyl

@@ -137,3 +137,21 @@ def test_colmajor_fresh_never_aliases_the_callers_tensor():
     R = torch.arange(12, dtype=torch.float64).reshape(3, 4)                     # row-major
     F2 = T.colmajor(R, torch.device("cpu"), fresh=True)
     assert F2.data_ptr() != R.data_ptr() and torch.equal(F2.t(), R)
+
+
+def test_noalloc_rejects_without_a_device(lib):
+    """trsyl_robust_noalloc checks its arguments and whether the problem's state fits its fixed
+    array on the host, before any device call: a problem too large for TRSYL_NOALLOC_BYTES gives
+    TRSYL_ENOSPACE, the precision form is refused (-12), bad sizes give their argument index."""
+    import paper_1905_10574_amd as T
+    L = T.lib()
+    o = T.make_opts()
+    fake = 256                                   # never dereferenced on these paths
+    args = lambda m, n: (m, n, fake, max(1, m), fake, max(1, n), fake, max(1, m), fake, fake, fake)
+    assert L.trsyl_robust_noalloc(*args(40000, 40000), ctypes.byref(o), None) == T.ENOSPACE
+    assert L.trsyl_robust_noalloc(*args(-1, 5), ctypes.byref(o), None) == -1
+    p = T.make_opts(precision="fp32_refine")
+    assert L.trsyl_robust_noalloc(*args(100, 100), ctypes.byref(p), None) == -12
+    bad = T.make_opts()
+    bad.tile_m = 8
+    assert L.trsyl_robust_noalloc(*args(100, 100), ctypes.byref(bad), None) == -12
