@@ -34,6 +34,15 @@
  *        4  the persistent scheduler's watchdog expired (a dependency never resolved)
  *     On status 2 or 3 the contents of C are unspecified.
  *   - Functions are reentrant: concurrent calls need distinct workspaces.
+ *   - Host memory: the persistent scheduler (trsyl_robust and the entry points built on it, the
+ *     batched solves) follows a static task order that the library computes on the host the first
+ *     time it meets a tiling shape (tile counts, tile sizes, slabs, workgroups) and keeps, for the
+ *     life of the process, in pinned host memory (hipHostMalloc, 8 bytes per task, e.g. 2 MB for
+ *     m = n = 8192 with tile 128; a merged list for each batched problem set), from which each call
+ *     copies it into the workspace on the stream.  A first call per shape therefore allocates
+ *     pinned host memory and runs the list-scheduling simulation; later calls reuse the list.  The
+ *     cache is never trimmed (a list may still be the source of a copy in flight).  The per-front
+ *     scheduler and trsyl_robust_noalloc use no task list.
  */
 #ifndef TRSYL_H
 #define TRSYL_H
