@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kThreads) k_front_solve(Plan Pk, int d)
 {
     const Plan P = uniform_plan(Pk);
     __shared__ SolveLds L;
-    if (plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure) return;
+    if (plan_skipped(P) || uniform(*(volatile int32_t *)P.status) >= kBadStructure) return;
     const int lmin = d - (P.pt - 1) > 0 ? d - (P.pt - 1) : 0;
     const int l = lmin + blockIdx.x;
     const int k = P.pt - 1 - (d - l);
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(kThreads) k_front_update(Plan Pk, int d, int k
 {
     const Plan P = uniform_plan(Pk);
     __shared__ UpdateLds L;
-    if (plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure) return;
+    if (plan_skipped(P) || uniform(*(volatile int32_t *)P.status) >= kBadStructure) return;
     const int lmin = d - (P.pt - 1) > 0 ? d - (P.pt - 1) : 0;
     const int ntgt = (kind == kTaskColUpdate) ? P.pt - 1 : P.qt - 1;
     const int slab = blockIdx.x % P.slabs;

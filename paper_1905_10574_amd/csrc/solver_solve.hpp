@@ -772,10 +772,12 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         const DevView vY = dev_view(Y, P.ldc, mr, nc);
         int done = 0;
         // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
-        if (!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016)
+        // (the magnitude test is made wave-uniform: both branches below enclose barriers)
+        const int spec = uniform(!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016 ? 1 : 0);
+        if (spec)
             done = uniform(tile_solve_fast(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));
         TRSYL_STAMP(stamp, 2);
-        if (!done && !(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016) {
+        if (!done && spec) {
             // the leaf-tiled robust solve (the fast path left Y untouched)
             if (threadIdx.x == 0) atomicAdd(&P.stats[2], 1u);
             const int es = uniform(tile_solve_scaled(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L));
