@@ -106,13 +106,30 @@ __device__ __forceinline__ void leaf_gemm(d4 &acc, const double *Aop, int64_t ld
     const double *Ar = Aop + (va ? r : 0);
     const double *Bc = Bop + (int64_t)(vb ? r : 0) * ldb;
     double af[8], bf[8];
+    // the lane's 4 k of each half of a chunk are adjacent in a column of Bop: two 16-byte loads
+    // per half for a chunk that lies below k1 (global memory needs only 8-byte alignment)
     auto load = [&](int kc, double (&a)[8], double (&b)[8]) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = kc + 16 * (j >> 2) + 4 * q + (j & 3);
             const int kk = k < k1 ? k : k0;
             a[j] = ldg(Ar + (int64_t)kk * lda);
-            b[j] = ldg(Bc + kk);
+        }
+        if (uniform(kc + 32 <= k1 ? 1 : 0)) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int kq = kc + 16 * h + 4 * q;
+                double2 x0, x1;
+                __builtin_memcpy(&x0, (const gdouble *)(Bc + kq), 16);
+                __builtin_memcpy(&x1, (const gdouble *)(Bc + kq + 2), 16);
+                b[4 * h + 0] = x0.x; b[4 * h + 1] = x0.y; b[4 * h + 2] = x1.x; b[4 * h + 3] = x1.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = kc + 16 * (j >> 2) + 4 * q + (j & 3);
+                b[j] = ldg(Bc + (k < k1 ? k : k0));
+            }
         }
     };
     load(k0, af, bf);

@@ -48,6 +48,7 @@ def test_adjoint_matches_oracle(T, m, n, tile):
     G = G.cpu().numpy()
     err = np.linalg.norm(G - Go) / np.linalg.norm(Go)
     assert err <= 1e-10, err
+    assert np.abs(G - Go).max() <= 1e-10 * np.abs(Go).max()
     # the adjoint equation itself, in long double on the host
     R = A.T @ G + G @ B.T - Wm
     assert np.linalg.norm(R) / (np.linalg.norm(Wm) + (np.linalg.norm(A) + np.linalg.norm(B)) * np.linalg.norm(G)) <= 1e-13

@@ -2,11 +2,14 @@
 CPU oracle.
 
 Gates (from the method's contract and the solve's error analysis):
-  * well-separated spectra: e == 0 on both sides and ||Y_gpu - Y_orc||_F / ||Y_orc||_F <= 1e-10;
+  * well-separated spectra: e == 0 on both sides, ||Y_gpu - Y_orc||_F / ||Y_orc||_F <= 1e-10 and,
+    entry by entry, max |Y_gpu - Y_orc| <= 1e-10 max |Y_orc|;
   * every case: all entries finite and <= Omega, eq. (9) residual <= 1e-13;
-  * growth inputs: e > 0, and the normalised solutions agree to within a bound derived from the
-    oracle's own spread between two valid tile orders (these inputs are ill-conditioned enough
-    that rounding order alone moves the forward solution; see the oracle tests).
+  * growth inputs: e > 0, eq. (9) by the oracle in long double, and the normalised solutions agree
+    to within ten times the oracle's own spread between two valid tile orders, or 1e-8 (these
+    inputs are ill-conditioned enough that rounding order alone moves the forward solution: at
+    m = n = 256 the spread is ~4e-4 and the GPU's difference ~4e-4; at the full 4096 size the
+    forward solution is not determined at all, see test_gpu_fullsize).
 """
 import math
 import sys
@@ -34,6 +37,13 @@ def T():
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / nb if nb else np.linalg.norm(a)
+
+
+def maxrel(a, b):
+    """Element-wise: max |a - b| over max |b| (a wrong small entry or block fails it even when the
+    Frobenius norm hides it)."""
+    mb = np.abs(b).max()
+    return np.abs(a - b).max() / mb if mb else np.abs(a).max()
 
 
 def normalised(Y):
@@ -79,7 +89,7 @@ def test_small_workload_vs_oracle(T, orc, seed):
     for sched in ("dag", "fronts"):
         Y, e, info = gpu_solve(T, A, B, C, tile=64, scheduler=sched)
         assert info == 0 and e == 0 and eo == 0
-        assert rel(Y, Yo) <= 1e-10
+        assert rel(Y, Yo) <= 1e-10 and maxrel(Y, Yo) <= 1e-10
         assert orc.relres(A, B, Y, e, C) <= 1e-13
 
 
@@ -95,6 +105,7 @@ def test_ragged_shapes_vs_oracle(T, orc, m, n, tile):
         Y, e, info = gpu_solve(T, A, B, C, tile=tile, scheduler=sched)
         assert info == 0 and e == 0
         assert rel(Y, Yo) <= 1e-10, (sched, rel(Y, Yo))
+        assert maxrel(Y, Yo) <= 1e-10, (sched, maxrel(Y, Yo))
     assert orc.relres(A, B, Y, e, C) <= 1e-13
 
 
@@ -103,7 +114,7 @@ def test_forced_robust_tile_solve_matches(T, orc):
     A, B, C = W.separated_problem(5, 200, 170, p2x2=0.3)
     Yo, eo, _ = orc.drsylv(A, B, C, 64)
     Y, e, info = gpu_solve(T, A, B, C, tile=64, flags=1)
-    assert info == 0 and e == 0 and rel(Y, Yo) <= 1e-10
+    assert info == 0 and e == 0 and rel(Y, Yo) <= 1e-10 and maxrel(Y, Yo) <= 1e-10
 
 
 def _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2):
@@ -116,7 +127,7 @@ def _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2):
     spread = rel(np.ldexp(n2, (s2 + eo2) - (so + eo)), no)
     err = rel(np.ldexp(ng, (sg + e) - (so + eo)), no)
     print(f"    growth: e_gpu={e} e_orc={eo} err={err:.2e} oracle spread={spread:.2e}")
-    assert err <= max(1e-8, 100 * spread)
+    assert err <= max(1e-8, 10 * spread)
 
 
 @pytest.mark.parametrize("size,tile", [(64, 16), (200, 64), (256, 64)])

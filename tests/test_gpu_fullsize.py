@@ -1,9 +1,25 @@
 """GPU checks at the configurations' full sizes, in the launch configuration the benchmark times
-(default options: tile 128, persistent DAG scheduler).  The oracle cannot solve these sizes
-within a test, so the checks are properties that hold at any size, evaluated by the oracle where
-it can: exact (long double) residual rows on a seeded sample of rows, the invariants of the robust
-method (finite, bounded by Omega, alpha < 1 on growth inputs), and the device eq. (9).
+(default options: tile 128, persistent DAG scheduler), against the CPU oracle (Alg. 4, Sec. 2.2):
+
+  * separated spectra, m = n = 8192 (no scaling, e = 0, so Y is the unique solution X):
+      - 4160 sampled entries against stored oracle values (tests/golden/separated_8192_seed0_
+        samples.txt, written by make_separated_8192.py from the oracle alone): |Y - X| <= 1e-10
+        max|X| entry by entry;
+      - the bottom-left 1024 x 1024 block of Y against the oracle's solution of the sub-problem it
+        solves on its own (that block depends only on the trailing rows of A, the leading columns
+        of B and the same block of C), element by element;
+      - exact (long double) residual rows on a seeded sample of rows, and the device eq. (9);
+  * growth, m = n = 4096, tiles 256 and 128: backward error only (exact residual rows by the oracle,
+    device eq. (9)) and the robust method's invariants -- the forward solution is not determined at
+    this size (see the test);
+  * the 256-problem batch: separated members against the oracle element-wise (1e-10 max|X|); growth
+    members by oracle residual rows, and after normalisation (1e-8) wherever the oracle's own
+    solutions for two tile sizes agree (the forward solution is determined);
+  * the 32-problem adjoint set: against the oracle's adjoint solve, element-wise.
 """
+import math
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +30,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 torch = pytest.importorskip("torch")
 OMEGA = 2.0 ** 1022
+HERE = os.path.dirname(os.path.abspath(__file__))
+THREADS = min(16, os.cpu_count() or 1)
 
 
 @pytest.fixture(scope="module")
@@ -26,8 +44,9 @@ def T():
 
 
 def _sampled_rows_check(A, B, Y, e, C, nrows=24, seed=0, tol=1e-13):
-    """Per-row eq. (9) on sampled rows, in long double by the oracle, with Y and alpha scaled by
-    the power of two at or above max |Y|."""
+    """The residual of eq. (9) restricted to a seeded sample of rows, formed exactly (long double)
+    by the oracle with Y and alpha scaled by the power of two at or above max |Y|, over eq. (9)'s
+    whole-matrix denominator (rows that hold only flushed-to-zero entries then count as exact)."""
     m, n = Y.shape
     ymax = np.abs(Y).max()
     shift = int(np.frexp(ymax)[1]) if ymax > 0 else 0
@@ -35,58 +54,142 @@ def _sampled_rows_check(A, B, Y, e, C, nrows=24, seed=0, tol=1e-13):
     rr, yy, cc = oracle.residual_rows(A, B, Y, e, C, rows, shift)
     nA = np.linalg.norm(np.triu(A, -1))
     nB = np.linalg.norm(np.triu(B, -1))
-    q = np.sqrt(rr) / ((nA + nB) * np.sqrt(yy) + np.sqrt(cc))
+    ys = np.linalg.norm(np.ldexp(Y, -shift))
+    cs = math.ldexp(float(np.linalg.norm(C)), -(e + shift)) if e + shift < 3000 else 0.0
+    den = (nA + nB) * ys + cs
+    assert den > 0
+    q = np.sqrt(rr) / den
     assert q <= tol, q
+
+
+def _normalised_agree(Y, e, Yo, eo, tol):
+    """Y 2^e and Yo 2^eo (both 2^-alpha-scaled representations of the same solution) agree after
+    normalisation to max |entry| in [0.5, 1)."""
+    sg = math.frexp(np.abs(Y).max())[1]
+    so = math.frexp(np.abs(Yo).max())[1]
+    assert abs((sg + e) - (so + eo)) <= 1
+    ng = np.ldexp(Y, (e - eo) - so)
+    no = np.ldexp(Yo, -so)
+    err = np.linalg.norm(ng - no) / np.linalg.norm(no)
+    assert err <= tol, err
+    return err
+
+
+def _tile_norms_ok(Y, A, B, t):
+    ro, co = oracle.tile_offsets(A, t), oracle.tile_offsets(B, t)
+    for k in range(len(ro) - 1):
+        for l in range(len(co) - 1):
+            blk = np.abs(Y[ro[k]:ro[k + 1], co[l]:co[l + 1]])
+            if blk.size:
+                assert blk.sum(axis=1).max() <= OMEGA
+
+
+def _block_start(T_, b):
+    """The nearest split point at or after b that does not cut a 2x2 block."""
+    return b + 1 if b > 0 and T_[b, b - 1] != 0.0 else b
 
 
 def test_separated_8192(T):
     A, B, C = W.config_separated(0)
+    m, n = C.shape
+    print("  gpu solve separated 8192 (default options)", flush=True)
     Y, e, info = T.solve(A, B, C)
     assert info == 0 and e == 0
     assert T.residual(A, B, Y, e, C) <= 1e-13
     Yn = Y.cpu().numpy()
     assert np.all(np.isfinite(Yn))
+    # stored oracle samples
+    path = os.path.join(HERE, "golden", "separated_8192_seed0_samples.txt")
+    lines = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    head = [ln for ln in open(path) if ln.startswith("# e =")][0]
+    xmax = float.fromhex(head.split("max|Y| = ")[1].split(",")[0])
+    ii = np.array([int(a) for a, _, _ in lines])
+    jj = np.array([int(b) for _, b, _ in lines])
+    xo = np.array([float.fromhex(c) for _, _, c in lines])
+    assert len(xo) == 4160
+    dif = np.abs(Yn[ii, jj] - xo).max()
+    print(f"    sampled entries: max |Y - X| = {dif:.3e} (max|X| = {xmax:.3e})", flush=True)
+    assert dif <= 1e-10 * xmax
+    # bottom-left block: the oracle solves A[r:, r:] Z + Z B[:c, :c] = C[r:, :c] on its own
+    r = _block_start(A, m - 1024)
+    c = _block_start(B, 1024)
+    Z, ez, rc = oracle.drsylv(np.asfortranarray(A[r:, r:]), np.asfortranarray(B[:c, :c]),
+                              np.asfortranarray(C[r:, :c]), 64, threads=THREADS)
+    assert ez == 0 and rc == 0
+    dz = np.abs(Yn[r:, :c] - Z).max()
+    print(f"    bottom-left {m - r} x {c} block: max |Y - Z| = {dz:.3e}", flush=True)
+    assert dz <= 1e-10 * np.abs(Z).max()
     _sampled_rows_check(A, B, Yn, e, C)
 
 
 @pytest.mark.parametrize("tile", [256, 128])
 def test_growth_4096(T, tile):
+    """At this size the growth input's condition number (about 2^80000) leaves the forward solution
+    undetermined to working precision: the oracle's own normalised solutions for tiles 128 and 256
+    differ completely (largest entries 2^80552 vs 2^80419).  The checks are therefore the backward
+    error -- exact residual rows by the oracle and the device eq. (9) -- and the invariants of the
+    robust method (finite, every tile norm <= Omega, e > 0)."""
     A, B, C = W.config_growth(0)
+    print(f"  gpu solve growth 4096 tile {tile}", flush=True)
     Y, e, info = T.solve(A, B, C, tile=tile)
     assert info in (0, 1) and e > 0
     Yn = Y.cpu().numpy()
     assert np.all(np.isfinite(Yn)) and np.abs(Yn).max() <= OMEGA
-    # every tile's infinity norm within Omega (row sums of each tile)
-    t = tile
-    for r0 in range(0, Yn.shape[0], t):
-        for c0 in range(0, Yn.shape[1], 4 * t):
-            blk = np.abs(Yn[r0:r0 + t + 1, c0:c0 + 4 * t])
-            assert np.all(blk.sum(axis=1) <= 4 * OMEGA)
+    _tile_norms_ok(Yn, A, B, tile)
     assert T.residual(A, B, Y, e, C) <= 1e-13
-    _sampled_rows_check(A, B, Yn, e, C)
+    _sampled_rows_check(A, B, Yn, e, C, nrows=64)
+    print(f"    e = {e}, largest entry 2^{math.frexp(np.abs(Yn).max())[1]}", flush=True)
 
 
 def test_batched_256(T):
+    """Separated members against the oracle entry by entry.  Growth members: exact residual rows by
+    the oracle (backward error), and, where the oracle's own solutions for two tile sizes agree
+    after normalisation to 1e-10 (the forward solution is determined), the GPU's too (1e-8)."""
     probs = W.config_batched(0)
     As = [p[1] for p in probs]
     Bs = [p[2] for p in probs]
     Cs = [p[3] for p in probs]
+    print("  gpu batched solve of the 256-problem set", flush=True)
     out = T.solve_batched(As, Bs, Cs)
-    for (kind, A, B, C), (Y, e, info) in zip(probs, out):
+    worst = {"separated": 0.0, "growth_determined": 0.0}
+    determined = 0
+    for i, ((kind, A, B, C), (Y, e, info)) in enumerate(zip(probs, out)):
         assert info in (0, 1)
-        if kind == "growth" and min(C.shape) >= 512:
-            assert e > 0
+        Yn = Y.cpu().numpy()
         if kind == "separated":
-            assert e == 0
-        assert T.residual(A, B, Y, e, C) <= 1e-13
+            Yo, eo, rc = oracle.drsylv(A, B, C, 64, threads=THREADS)
+            assert e == 0 and eo == 0
+            d = np.abs(Yn - Yo).max() / np.abs(Yo).max()
+            assert d <= 1e-10, (i, d)
+            worst["separated"] = max(worst["separated"], d)
+        else:
+            if min(C.shape) >= 512:
+                assert e > 0
+            assert np.all(np.isfinite(Yn)) and np.abs(Yn).max() <= OMEGA
+            _sampled_rows_check(A, B, Yn, e, C, nrows=8, seed=i)
+            Yo, eo, _ = oracle.drsylv(A, B, C, 64, threads=THREADS)
+            Y2, e2, _ = oracle.drsylv(A, B, C, 48, threads=THREADS)
+            try:
+                _normalised_agree(Y2, e2, Yo, eo, 1e-10)
+            except AssertionError:
+                continue                       # forward solution not determined at this size
+            determined += 1
+            d = _normalised_agree(Yn, e, Yo, eo, 1e-8)
+            worst["growth_determined"] = max(worst["growth_determined"], d)
+    print(f"    worst difference to the oracle: {worst}; growth members with a determined solution: "
+          f"{determined} of {sum(1 for p in probs if p[0] == 'growth')}", flush=True)
 
 
 def test_adjoint_32(T):
     probs = W.config_adjoint(0)
+    worst = 0.0
     for i, (A, B, C, Wm) in enumerate(probs):
         G, e, info = T.adjoint(A, B, Wm)
         assert info == 0 and e == 0
         G = G.cpu().numpy()
-        R = A.T @ G + G @ B.T - Wm
-        q = np.linalg.norm(R) / ((np.linalg.norm(A) + np.linalg.norm(B)) * np.linalg.norm(G) + np.linalg.norm(Wm))
-        assert q <= 1e-13, (i, q)
+        Go, eo, rc = oracle.adjoint(A, B, Wm, 64, threads=THREADS)
+        assert eo == 0
+        d = np.abs(G - Go).max() / np.abs(Go).max()
+        assert d <= 1e-10, (i, d)
+        worst = max(worst, d)
+    print(f"    adjoint set: worst element-wise difference to the oracle {worst:.2e}", flush=True)
