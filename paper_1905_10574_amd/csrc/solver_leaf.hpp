@@ -2,23 +2,25 @@
 // (a diagonal block pair of the tile, Sec. 2.1's RobustSyl without scaling, certified by the
 // caller), one wave per leaf.
 //
-// Lane (c, q) = c + 16 q holds column c and rows q, q + 4, q + 8, q + 12 of the leaf.  The solve
-// walks the block anti-diagonals s = 0, 1, ...: the blocks on diagonal s become final, then every
-// entry subtracts the contributions of the block solved at step s in its block column (rows
-// below it) and in its block row (columns left of it).  Which block that is at step s is looked
-// up in four small offset tables built once per leaf.  Updates are not masked: once an entry is
-// final, the sources the tables give it lie in its own block or beyond, where A and B hold exact
-// zeros outside the block, so its register keeps only the (tiny) residual of its block.
+// Layout.  The leaf's rows are grouped into at most 8 row pairs: each 2x2 block of A_l is a pair,
+// and the 1x1 blocks are paired in order of appearance (an odd one out is paired with nothing).
+// The columns are grouped into column pairs the same way from B_l.  Lane rho + 8 kappa holds the
+// four entries (row pair rho) x (column pair kappa), so every 1x1, 2x1, 1x2 or 2x2 block of
+// unknowns lies inside one lane.  The inverse of every block system the lane owns (Sec. 2.1's
+// 1, 2 and 4-unknown systems, factored by Gaussian elimination with complete pivoting and
+// applied to the unit vectors) forms a 4 x 4 block-diagonal matrix W held in the lane's
+// registers, so a block's unknowns are W times its right-hand sides, with no cross-lane traffic.
 //
-// Every division of the step loop is taken out of it: 1x1 blocks keep the reciprocal of
-// a_rr + b_cc, and the 2- and 4-unknown block systems (Sec. 2.1) are factored once per leaf by
-// Gaussian elimination with complete pivoting, one block per lane, and the factors applied to
-// the unit vectors, which stores each block's inverse in LDS.  Every lane keeps, in registers,
-// the row of that inverse belonging to the next entry it finalises, loaded at least two steps
-// ahead; at a step that solves a multi-entry block, each lane of the block gathers the block's
-// right-hand sides by cross-lane permutes and takes its unknown as one short dot product, so a
-// step needs the permutes and one LDS round trip (publish the solved values, read the sources).
-// A block beyond the stored slots is factored and solved at its step instead.
+// Sweep.  Step s makes the blocks on block anti-diagonal s final.  Every step each lane writes
+// W times its four right-hand sides to the leaf buffer (an entry becomes correct at its own step
+// and is only read from then on), then reads the two source blocks of each entry (the block
+// solved at step s in its block column, the block solved at step s in its block row) and
+// subtracts their contributions.  For the duration of the sweep the diagonal blocks of A_l and
+// B_l are set to zero: an entry's only sources after its own step lie in its own block or beyond,
+// so its right-hand side, and with it the value written for it, stays fixed from then on.
+// Source positions come from two small offset tables per leaf; a 1x1 source block's second row
+// (column) is the leaf buffer's zero row (column) 16, which no lane writes (patch entries outside
+// the leaf write to a per-lane sink).
 #pragma once
 #include "device_common.hpp"
 #include "plan.hpp"
@@ -27,27 +29,22 @@ namespace trsyl {
 
 constexpr int kLd = 17;              // leading dimension of the 17 x 17 leaf buffers
 constexpr int kSlab = kLd * 8;       // bytes per column of a leaf buffer
-constexpr int kF2Slots = 64;         // stored factorisations of 2-unknown blocks per leaf
-constexpr int kF4Slots = 16;         // stored factorisations of 4-unknown blocks per leaf
-constexpr uint32_t kNoSlot = 255u;
-constexpr int kTab = 80;             // source-table words: 16 before, 16 blocks, 48 after
+constexpr int kTab = 80;             // source-table entries: 16 before, 16 blocks, 48 after
 constexpr int kTabIdle = 32;         // table index of step 0 for an entry outside the leaf
 
 struct LeafLds {
     double R[17 * kLd];    // Y(r, k) at [k * 17 + r]: the right-hand side, then the solution
     double Al[17 * kLd];   // A_l(r, k) at [k * 17 + r]
-    double Bl[17 * kLd];   // B_l(r, k) at [k * 17 + r]
-    // Row 16 and column 16 of R, Al, Bl hold zeros.  Source tables, kTab words each: word 16 + k
-    // describes the k-th source block, every other word points at the zero row / column 16.
-    // A word packs the byte offsets of the block's first and second row (column); a 1x1 block's
-    // second one is the zero row (column).
-    uint32_t tcA[kTab];      // k-th block row from the bottom, offsets into Al columns (r * kSlab)
-    uint32_t tcY[kTab];      //   the same rows as offsets inside a column of R (r * 8)
-    uint32_t trY[kTab];      // k-th block column from the left, offsets into R columns (c * kSlab)
-    uint32_t trB[kTab];      //   the same columns as offsets inside a column of Bl (c * 8)
-    double f2[kF2Slots][4];      // inverses of 2-unknown blocks, row k at [2k], [2k + 1]
-    double f4[kF4Slots][16];     // inverses of 4-unknown blocks in position order, row t at [4t ..]
-    uint8_t slot[16 * 16];       // inverse slot of the block with top-left entry (r, c)
+    double Bl[17 * kLd + 1];   // B_l(r, k) at [k * 17 + r]; one zero after the last column
+    // Row 16 and column 16 of R, Al, Bl hold zeros.  Source tables, kTab entries each: entry
+    // 16 + k describes the k-th source block, every other entry points at the zero row / column.
+    uint2 tcol[kTab];   // k-th block row from the bottom, first row r0, second r1 (16 for 1x1):
+                        //   x = r0 * kSlab (a column of Al), y = r0 * 8 | r1 * 8 << 16 (rows of R)
+    uint2 trow[kTab];   // k-th block column from the left, first column c0, second c1:
+                        //   x = c0 * 8 (rows of a column of Bl), y = c0 * kSlab | c1 * kSlab << 16
+    uint8_t pr[2][8];   // row pairs: first and second row (16: none)
+    uint8_t pc[2][8];   // column pairs
+    double sink[64];    // per lane: where the values of patch entries outside the leaf go
 };
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -232,105 +229,92 @@ __device__ __forceinline__ LeafMasks leaf_masks(const LeafLds &L, int nr, int nc
     M.nb = __popc(M.cmask);
     return M;
 }
-// Steps that solve a block with 2 or 4 unknowns: block (Ib, Jb) is final at step
-// (na - 1 - Ib) + Jb, so a 2x2 block row Ib marks steps na - 1 - Ib + [0, nb) and a 2x2 block
-// column Jb marks steps Jb + [0, na).
-__device__ __forceinline__ uint32_t multi_steps(const LeafMasks &M)
-{
-    uint32_t ms = 0u;
-    for (uint32_t x = M.m2; x; x &= x - 1u) {
-        const int r = __ffs((int)x) - 1;
-        const int Ib = __popc(M.rmask & ((1u << r) - 1u));
-        ms |= ((1u << M.nb) - 1u) << (M.na - 1 - Ib);
-    }
-    for (uint32_t x = M.n2; x; x &= x - 1u) {
-        const int c = __ffs((int)x) - 1;
-        const int Jb = __popc(M.cmask & ((1u << c) - 1u));
-        ms |= ((1u << M.na) - 1u) << Jb;
-    }
-    return ms;
-}
-__device__ __forceinline__ int kth_bit(uint32_t m, int k)   // index of the k-th set bit (k < 16)
-{
-    for (int t = 0; t < k && t < 16; ++t) m &= m - 1u;
-    return __ffs((int)m) - 1;
-}
 
 // ---------------------------------------------------------------------------------------------
-// Per-leaf set-up by its wave: the source tables and the factorisations of every 2- and
-// 4-unknown block (one block per lane; blocks beyond the slots are factored at their step).
-// Returns 0 in a lane whose factorisation met a pivot below smin.
+// The lane's patch: rows r[x] and columns c[y] of its four entries t = x + 2 y (16: none), and
+// W, the inverse of every block system inside the patch (zero elsewhere).  ok = 0 when a pivot
+// of those systems fell below smin.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ int leaf_setup(LeafLds &L, const LeafMasks &M, double smin)
+struct LeafPatch {
+    int r[2], c[2];
+    double w[4][4];
+    int ok;
+};
+
+// Per-leaf set-up by its wave: row / column pairs (lanes 0..15 one row each, lanes 16..31 one
+// column each), the source tables, then every lane's patch and block inverses.
+__device__ __forceinline__ LeafPatch leaf_setup(LeafLds &L, const LeafMasks &M, double smin)
 {
     const int lane = threadIdx.x & 63;
-    constexpr uint32_t zA = (16u * kSlab) | ((16u * kSlab) << 16), zY = (16u * 8u) | ((16u * 8u) << 16);
+    constexpr uint32_t zA = 16u * kSlab, zY = (16u * 8u) | ((16u * 8u) << 16);
+    constexpr uint32_t zB = 16u * 8u, zZ = (16u * kSlab) | ((16u * kSlab) << 16);
     for (int t = lane; t < kTab; t += 64) {
-        L.tcA[t] = zA;
-        L.tcY[t] = zY;
-        L.trY[t] = zA;
-        L.trB[t] = zY;
+        L.tcol[t] = make_uint2(zA, zY);
+        L.trow[t] = make_uint2(zB, zZ);
     }
-    ((uint32_t *)L.slot)[lane] = 0xFFFFFFFFu;
+    if (lane < 16) (&L.pr[0][0])[lane] = 16;
+    else if (lane < 32) (&L.pc[0][0])[lane - 16] = 16;
+    if (lane == 0) L.Bl[17 * kLd] = 0.0;
     wave_sync_lds();
-    if (lane < 16) {
-        const uint32_t below = (1u << lane) - 1u;
-        if ((M.rmask >> lane) & 1u) {
-            const int k = M.na - 1 - __popc(M.rmask & below);
-            const uint32_t r1 = ((M.m2 >> lane) & 1u) ? lane + 1 : 16;
-            L.tcA[16 + k] = (uint32_t)(lane * kSlab) | ((r1 * kSlab) << 16);
-            L.tcY[16 + k] = (uint32_t)(lane * 8) | ((r1 * 8) << 16);
-        }
-        if ((M.cmask >> lane) & 1u) {
-            const int k = __popc(M.cmask & below);
-            const uint32_t c1 = ((M.n2 >> lane) & 1u) ? lane + 1 : 16;
-            L.trY[16 + k] = (uint32_t)(lane * kSlab) | ((c1 * kSlab) << 16);
-            L.trB[16 + k] = (uint32_t)(lane * 8) | ((c1 * 8) << 16);
+    if (lane < 32) {
+        const bool isC = lane >= 16;
+        const int r = lane & 15;
+        const uint32_t mask = isC ? M.cmask : M.rmask, two = isC ? M.n2 : M.m2;
+        const uint32_t one = mask & ~two;
+        if ((mask >> r) & 1u) {
+            const uint32_t below = (1u << r) - 1u;
+            const int n2b = __popc(two & below), k1 = __popc(one & below);
+            const bool is2 = (two >> r) & 1u;
+            const uint32_t r1 = is2 ? (uint32_t)r + 1u : 16u;
+            if (!isC) {
+                const int k = M.na - 1 - __popc(mask & below);
+                L.tcol[16 + k] = make_uint2((uint32_t)r * kSlab, ((uint32_t)r * 8u) | ((r1 * 8u) << 16));
+            } else {
+                const int k = __popc(mask & below);
+                L.trow[16 + k] = make_uint2((uint32_t)r * 8u, ((uint32_t)r * kSlab) | ((r1 * kSlab) << 16));
+            }
+            // pairs are numbered in the order they open: at a 2x2 block, and at every other 1x1
+            uint8_t (*Pr)[8] = isC ? L.pc : L.pr;
+            if (is2) {
+                const int pi = n2b + ((k1 + 1) >> 1);
+                Pr[0][pi] = (uint8_t)r;
+                Pr[1][pi] = (uint8_t)(r + 1);
+            } else if (!(k1 & 1)) {
+                Pr[0][n2b + (k1 >> 1)] = (uint8_t)r;
+            } else {
+                const int rp = 31 - __clz(one & below);    // the 1x1 block that opened this pair
+                Pr[1][__popc(two & ((1u << rp) - 1u)) + ((k1 - 1) >> 1)] = (uint8_t)r;
+            }
         }
     }
+    wave_sync_lds();
+    LeafPatch P;
+    const int rho = lane & 7, kap = lane >> 3;
+    P.r[0] = L.pr[0][rho];
+    P.r[1] = L.pr[1][rho];
+    P.c[0] = L.pc[0][kap];
+    P.c[1] = L.pc[1][kap];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) P.w[i][j] = 0.0;
     int ok = 1;
-    const uint32_t m1 = M.rmask & ~M.m2, n1 = M.cmask & ~M.n2;
-    const int A2 = __popc(M.m2), A1 = __popc(m1), B2 = __popc(M.n2), B1 = __popc(n1);
-    // 2-unknown blocks: a 2x2 A-block with a 1x1 B-block (rows), then 1x1 with 2x2 (columns)
-    if (lane < A2 * B1 + A1 * B2) {
-        const bool rows = lane < A2 * B1;
-        const int j = rows ? lane : lane - A2 * B1;
-        const int nbj = rows ? B1 : B2;              // >= 1 here
-        const int ra = kth_bit(rows ? M.m2 : m1, j / nbj);
-        const int cb = kth_bit(rows ? n1 : M.n2, j % nbj);
-        const double arr = L.Al[ra * kLd + ra], bcc = L.Bl[cb * kLd + cb];
-        Factor2 F;
-        bool good;
-        if (rows)   // (A11 + b I) z = r over the two rows
-            good = factor2_cp(arr + bcc, L.Al[(ra + 1) * kLd + ra], L.Al[ra * kLd + ra + 1],
-                              L.Al[(ra + 1) * kLd + ra + 1] + bcc, smin, F);
-        else        // z (a I + B11) = r over the two columns
-            good = factor2_cp(arr + bcc, L.Bl[cb * kLd + cb + 1], L.Bl[(cb + 1) * kLd + cb],
-                              arr + L.Bl[(cb + 1) * kLd + cb + 1], smin, F);
-        if (!good) ok = 0;
-        // the inverse's columns: the factors applied to the unit vectors
-        double x00 = 1.0, x10 = 0.0, x01 = 0.0, x11 = 1.0;
-        apply2(F, x00, x10);
-        apply2(F, x01, x11);
-        L.f2[lane][0] = x00;
-        L.f2[lane][1] = x01;
-        L.f2[lane][2] = x10;
-        L.f2[lane][3] = x11;
-        L.slot[ra * 16 + cb] = (uint8_t)lane;
-    }
-    if (lane < A2 * B2 && lane < kF4Slots) {
-        const int ra = kth_bit(M.m2, lane / B2), cb = kth_bit(M.n2, lane % B2);
+    const int ra = P.r[0], ca = P.c[0];
+    const bool R2 = ra < 16 && ((M.m2 >> ra) & 1u);
+    const bool C2 = ca < 16 && ((M.n2 >> ca) & 1u);
+    if (R2 && C2) {
+        // 4 unknowns (Sec. 2.1's Kronecker system of a 2x2 block pair), position t = x + 2 y
         double a[4], b[4], f[16];
         uint32_t pm;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int p = t & 1, pp = t >> 1;
             a[t] = L.Al[(ra + pp) * kLd + ra + p];
-            b[t] = L.Bl[(cb + pp) * kLd + cb + p];
+            b[t] = L.Bl[(ca + pp) * kLd + ca + p];
         }
         if (!factor4_cp(a, b, smin, f, pm)) ok = 0;
-        // column j of the inverse: the right-hand side e_j in the factorisation's row order,
-        // the unknowns come back in its column order
+        // column j of the inverse: e_j in the factorisation's row order, the unknowns come back
+        // in its column order
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             double v[4];
@@ -338,228 +322,200 @@ __device__ __forceinline__ int leaf_setup(LeafLds &L, const LeafMasks &M, double
             for (int t = 0; t < 4; ++t) v[t] = ((pm >> (2 * t)) & 3u) == (uint32_t)j ? 1.0 : 0.0;
             apply4(f, v);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) L.f4[lane][4 * ((pm >> (8 + 2 * t)) & 3u) + j] = v[t];
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t u = (pm >> (8 + 2 * t)) & 3u;
+#pragma unroll
+                for (int uu = 0; uu < 4; ++uu)
+                    if (u == (uint32_t)uu) P.w[uu][j] = v[t];
+            }
         }
-        L.slot[ra * 16 + cb] = (uint8_t)lane;
+    } else if (R2) {
+        // (A11 + b_cc I) z = g over the block's two rows, for each column of the patch
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int c = P.c[y];
+            if (c < 16) {
+                const double bcc = L.Bl[c * kLd + c];
+                Factor2 F;
+                if (!factor2_cp(L.Al[ra * kLd + ra] + bcc, L.Al[(ra + 1) * kLd + ra], L.Al[ra * kLd + ra + 1],
+                                L.Al[(ra + 1) * kLd + ra + 1] + bcc, smin, F))
+                    ok = 0;
+                double x00 = 1.0, x10 = 0.0, x01 = 0.0, x11 = 1.0;
+                apply2(F, x00, x10);
+                apply2(F, x01, x11);
+                P.w[2 * y][2 * y] = x00;
+                P.w[2 * y][2 * y + 1] = x01;
+                P.w[2 * y + 1][2 * y] = x10;
+                P.w[2 * y + 1][2 * y + 1] = x11;
+            }
+        }
+    } else if (C2) {
+        // z (a_rr I + B11) = g over the block's two columns, for each row of the patch
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int r = P.r[x];
+            if (r < 16) {
+                const double arr = L.Al[r * kLd + r];
+                Factor2 F;
+                if (!factor2_cp(arr + L.Bl[ca * kLd + ca], L.Bl[ca * kLd + ca + 1], L.Bl[(ca + 1) * kLd + ca],
+                                arr + L.Bl[(ca + 1) * kLd + ca + 1], smin, F))
+                    ok = 0;
+                double x00 = 1.0, x10 = 0.0, x01 = 0.0, x11 = 1.0;
+                apply2(F, x00, x10);
+                apply2(F, x01, x11);
+                P.w[x][x] = x00;
+                P.w[x][x + 2] = x01;
+                P.w[x + 2][x] = x10;
+                P.w[x + 2][x + 2] = x11;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int r = P.r[t & 1], c = P.c[t >> 1];
+            if (r < 16 && c < 16) {
+                const double d = L.Al[r * kLd + r] + L.Bl[c * kLd + c];
+                if (fabs(d) < smin) ok = 0;
+                P.w[t][t] = 1.0 / d;
+            }
+        }
     }
-    wave_sync_lds();
-    return ok;
+    P.ok = ok;
+    return P;
 }
 
 // ---------------------------------------------------------------------------------------------
-// The step loop.  Returns 0 in a lane where a pivot fell below smin or a value it produced
-// exceeded Tc (the first non-finite value is an infinity, which the running maximum keeps).
-// With vmax_out, the lane's largest magnitude is stored there instead and only the pivots
-// decide the return value.  MULTI = false is the loop of a leaf made of 1x1 blocks only.
+// The sweep.  MODE bit 0: the leaf has 2x2 blocks of A_l, bit 1: of B_l (W's coupling pattern).
+// Returns 0 when a value it produced (a right-hand side after an update, or a value written)
+// exceeded Tc or was not finite; with vmax_out the largest magnitude (infinity for a non-finite
+// value) is stored there instead and 1 is returned.
 // ---------------------------------------------------------------------------------------------
-template <bool MULTI>
-__device__ __forceinline__ int leaf_solve_t(LeafLds &L, int nr, int nc, double smin, double Tc,
-                                            const LeafMasks &M, double *vmax_out)
+template <int MODE>
+__device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, const LeafMasks &M, int nr, int nc,
+                                            double Tc, double *vmax_out)
 {
-    constexpr int E = 4;
     const int lane = threadIdx.x & 63;
-    const int c = lane & 15, q = lane >> 4;
-    const uint32_t rmask = M.rmask, cmask = M.cmask, m2 = M.m2, n2 = M.n2;
-    const int na = M.na, steps = M.na + M.nb - 1;
-    const uint32_t msteps = multi_steps(M);
-    const bool cvalid = c < nc;
-    const uint32_t cle = cmask & ((2u << c) - 1u);
-    const int Jc = __popc(cle) - 1;                  // my block column
-    const int cb0 = cle ? 31 - __clz(cle) : 0;       // its first column
-    const int csz = 1 + ((n2 >> cb0) & 1);
-    const double bcc = L.Bl[c * kLd + c];
-    const int ctab = cvalid ? 16 - Jc : kTabIdle;    // table index of step 0
-
-    int ok = 1;
-    double vmax = 0.0;
-    double acc[E], rdd[E];
-    int fin[E], rtab[E];
-    uint32_t info[E];                                // kind | pos << 2 | slot << 4 | block lane << 12
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int r = q + 4 * i;
-        const bool valid = cvalid && r < nr;
-        const uint32_t rle = rmask & ((2u << r) - 1u);
-        const int Ir = __popc(rle) - 1;
-        const int rb0 = rle ? 31 - __clz(rle) : 0;
-        const int rsz = 1 + ((m2 >> rb0) & 1);
-        const int rowst = na - 1 - Ir;               // first step with a row source
-        fin[i] = valid ? rowst + Jc : -1;            // step at which the entry is final
-        rtab[i] = valid ? 16 - rowst : kTabIdle;
-        acc[i] = L.R[c * kLd + r];
-        const uint32_t kind = (rsz == 2 ? 1u : 0u) + (csz == 2 ? 2u : 0u);
-        const uint32_t pos = (uint32_t)((r - rb0) + 2 * (c - cb0));
-        const uint32_t sl = (valid && kind) ? L.slot[rb0 * 16 + cb0] : kNoSlot;
-        const uint32_t bl = (uint32_t)((cb0 + 16 * (rb0 & 3)) & 63);
-        info[i] = kind | (pos << 2) | (sl << 4) | (bl << 12);
-        rdd[i] = 1.0;
-        if (valid && kind == 0) {
-            const double dd = L.Al[r * kLd + r] + bcc;
-            if (fabs(dd) < smin) ok = 0;
-            rdd[i] = 1.0 / dd;
-        }
+    const int steps = M.na + M.nb - 1;
+    // set the diagonal blocks of A_l (lanes 0..15, row r) and B_l (lanes 16..31, column c) to
+    // zero for the sweep; the lane keeps the values it cleared
+    double *dz = lane < 16 ? L.Al : L.Bl;
+    const uint32_t dtwo = lane < 16 ? M.m2 : M.n2;
+    const int di = lane & 15;
+    int zo0 = -1, zo1 = -1;
+    double zv0 = 0.0, zv1 = 0.0;
+    if (lane < 32 && di < (lane < 16 ? nr : nc)) {
+        zo0 = di * kLd + di;
+        int pt = -1;                                   // the other row (column) of a 2x2 block
+        if ((dtwo >> di) & 1u) pt = di + 1;
+        else if (di > 0 && ((dtwo >> (di - 1)) & 1u)) pt = di - 1;
+        if (pt >= 0) zo1 = lane < 16 ? pt * kLd + di : di * kLd + pt;
     }
-    // cn: the row of the block inverse of the entry this lane finalises next, over the block's
-    // positions p + 2 pp (a 1x1 block: its reciprocal in cn[0]); a block without a stored inverse
-    // leaves zeros and is solved from its factorisation at its step
-    double cn[4] = {0.0, 0.0, 0.0, 0.0};
-    auto fetch = [&](uint32_t inf, double rd) __attribute__((always_inline)) {
-        const uint32_t kind = inf & 3u, pos = (inf >> 2) & 3u, sl = (inf >> 4) & 255u;
-        if (kind == 0u) {
-            cn[0] = rd; cn[1] = 0.0; cn[2] = 0.0; cn[3] = 0.0;
-        } else if (sl == kNoSlot) {
-            cn[0] = 0.0; cn[1] = 0.0; cn[2] = 0.0; cn[3] = 0.0;
-        } else if (kind == 3u) {
+    if (zo0 >= 0) { zv0 = dz[zo0]; dz[zo0] = 0.0; }
+    if (zo1 >= 0) { zv1 = dz[zo1]; dz[zo1] = 0.0; }
+    // tables, offsets and right-hand sides of the patch
+    int rtab[2], ctab[2];
+    uint32_t rof[2], cof[2];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) cn[t] = L.f4[sl][4 * pos + t];
-        } else {
-            const uint32_t k = kind == 1u ? pos : pos >> 1;
-            const double x0 = L.f2[sl][2 * k], x1 = L.f2[sl][2 * k + 1];
-            cn[0] = x0;
-            cn[1] = kind == 1u ? x1 : 0.0;
-            cn[2] = kind == 1u ? 0.0 : x1;
-            cn[3] = 0.0;
-        }
-    };
-    if constexpr (MULTI) {
-        // entries finalise from the last valid one (largest row) upwards
-        uint32_t finf = 0u;
-        double frd = 1.0;
-        bool any = false;
-#pragma unroll
-        for (int i = 0; i < E; ++i)
-            if (fin[i] >= 0) { finf = info[i]; frd = rdd[i]; any = true; }
-        if (any) fetch(finf, frd);
+    for (int x = 0; x < 2; ++x) {
+        const int r = P.r[x];
+        rof[x] = (uint32_t)r * 8u;
+        rtab[x] = kTabIdle;
+        if (r < 16) rtab[x] = 16 - (M.na - 1 - (__popc(M.rmask & ((2u << r) - 1u)) - 1));
     }
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+        const int c = P.c[y];
+        cof[y] = (uint32_t)c * kSlab;
+        ctab[y] = kTabIdle;
+        if (c < 16) ctab[y] = 16 - (__popc(M.cmask & ((2u << c) - 1u)) - 1);
+    }
+    wave_sync_lds();
     const char *Rb = (const char *)L.R, *Ab = (const char *)L.Al, *Bb = (const char *)L.Bl;
-    const char *Rc = Rb + c * kSlab, *Bc = Bb + c * kSlab;
-    // Software pipeline: the source tables of step s + 2 and the coefficients of step s + 1 are
-    // read while step s's updates run (neither depends on the values being solved).
-    struct Tabs { uint32_t ta, ty, tb[E], tz[E]; };
-    struct Coef { double a0[E], a1[E], b0[E], b1[E]; };
-    auto tables = [&](int s, Tabs &T) {
-        T.ta = L.tcA[ctab + s];
-        T.ty = L.tcY[ctab + s];
+    char *Rw = (char *)L.R;
+    double acc[4];
+    uint32_t wof[4];     // where entry t's value is written: its place in R, or the lane's sink
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            T.tb[i] = L.trB[rtab[i] + s];
-            T.tz[i] = L.trY[rtab[i] + s];
-        }
+    for (int t = 0; t < 4; ++t) {
+        acc[t] = lds_at(Rb, cof[t >> 1] + rof[t & 1]);
+        const bool real = P.r[t & 1] < 16 && P.c[t >> 1] < 16;
+        wof[t] = real ? cof[t >> 1] + rof[t & 1] : (uint32_t)((const char *)&L.sink[lane] - Rb);
+    }
+    double vmax = 0.0;
+    // software pipeline: the tables of step s + 2 and the coefficients of step s + 1 are read
+    // while step s's updates run
+    struct Tabs { uint2 col[2], row[2]; };
+    struct Coef { double a0[4], a1[4], b0[4], b1[4]; };
+    auto tables = [&](int s, Tabs &T) {
+#pragma unroll
+        for (int y = 0; y < 2; ++y) T.col[y] = L.tcol[ctab[y] + s];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) T.row[x] = L.trow[rtab[x] + s];
     };
     auto coefs = [&](const Tabs &T, Coef &C) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            C.a0[i] = lds_at(Ab, (T.ta & 0xffffu) + 8 * (q + 4 * i));
-            C.a1[i] = lds_at(Ab, (T.ta >> 16) + 8 * (q + 4 * i));
-            C.b0[i] = lds_at(Bc, T.tb[i] & 0xffffu);
-            C.b1[i] = lds_at(Bc, T.tb[i] >> 16);
+        for (int t = 0; t < 4; ++t) {
+            const int x = t & 1, y = t >> 1;
+            const char *pa = Ab + T.col[y].x + rof[x];            // A(r_x, r0), A(r_x, r0 + 1)
+            C.a0[t] = lds_at(pa, 0);
+            C.a1[t] = lds_at(pa, kSlab);
+            const char *pb = Bb + cof[y] + T.row[x].x;            // B(c0, c_y), B(c0 + 1, c_y)
+            C.b0[t] = lds_at(pb, 0);
+            C.b1[t] = lds_at(pb, 8);
         }
     };
-    // one step: finalise the entries of step s, publish them, read the values the updates need,
-    // start the loads of the next operands (into the table set just consumed and the free
-    // coefficient set), then apply the updates.  Two steps per loop trip swap the roles of the
-    // register sets, so no operand is copied between trips.
+    double ynan = 0.0;   // stays 0 unless a value written was not finite
     auto step = [&](int s, Tabs &Tc_, const Tabs &Tn, const Coef &Cc, Coef &Cn) __attribute__((always_inline)) {
-        // the entry this lane finalises at step s, if any (at most one: its rows lie in distinct
-        // block rows)
-        double accf = 0.0, rdf = 1.0;
-        int rf = -1, fi = -1;
-        uint32_t inf = 0u;
+        // W times the right-hand sides: final for the blocks of step s and every earlier one
+        double yv[4];
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            if (fin[i] == s) {
-                accf = acc[i]; rf = q + 4 * i; fi = i;
-                if constexpr (MULTI) inf = info[i];
-                else rdf = rdd[i];
+        for (int t = 0; t < 4; ++t) {
+            double v;
+            if constexpr (MODE == 3) {
+                v = P.w[t][0] * acc[0];
+                v = fma(P.w[t][1], acc[1], v);
+                v = fma(P.w[t][2], acc[2], v);
+                v = fma(P.w[t][3], acc[3], v);
+            } else if constexpr (MODE == 1) {
+                v = fma(P.w[t][t | 1], acc[t | 1], P.w[t][t & 2] * acc[t & 2]);
+            } else if constexpr (MODE == 2) {
+                v = fma(P.w[t][(t & 1) + 2], acc[(t & 1) + 2], P.w[t][t & 1] * acc[t & 1]);
+            } else {
+                v = P.w[t][t] * acc[t];
             }
-        }
-        double yf;
-        if (MULTI && ((msteps >> s) & 1u)) {
-            const uint32_t kind = inf & 3u, pos = (inf >> 2) & 3u, sl = (inf >> 4) & 255u;
-            const int bl = (int)(inf >> 12);
-            // the block's right-hand sides in position order p + 2 pp (entry (rb0 + p, cb0 + pp)
-            // sits in lane cb0 + pp + 16 ((rb0 + p) & 3)); positions outside the block read as 0
-            double g[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) g[t] = __shfl(accf, (bl + 16 * (t & 1) + (t >> 1)) & 63, 64);
-            const double g1 = (kind & 1u) ? g[1] : 0.0, g2 = (kind & 2u) ? g[2] : 0.0;
-            const double g3 = kind == 3u ? g[3] : 0.0;
-            yf = fma(cn[3], g3, fma(cn[2], g2, fma(cn[1], g1, cn[0] * g[0])));
-            if (rf >= 0 && kind != 0u && sl == kNoSlot) {
-                // no stored inverse: factor the block here
-                const int ra = rf - (int)(pos & 1u), cb = c - (int)(pos >> 1);
-                if (kind != 3u) {
-                    const double arr = L.Al[ra * kLd + ra], bb = L.Bl[cb * kLd + cb];
-                    Factor2 F;
-                    bool good;
-                    if (kind == 1u)
-                        good = factor2_cp(arr + bb, L.Al[(ra + 1) * kLd + ra], L.Al[ra * kLd + ra + 1],
-                                          L.Al[(ra + 1) * kLd + ra + 1] + bb, smin, F);
-                    else
-                        good = factor2_cp(arr + bb, L.Bl[cb * kLd + cb + 1], L.Bl[(cb + 1) * kLd + cb],
-                                          arr + L.Bl[(cb + 1) * kLd + cb + 1], smin, F);
-                    if (!good) ok = 0;
-                    double v0 = g[0], v1 = kind == 1u ? g[1] : g[2];
-                    apply2(F, v0, v1);
-                    yf = pos == 0u ? v0 : v1;
-                } else {
-                    double a[4], b[4], f[16], w[4];
-                    uint32_t pm2;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int p = t & 1, pp = t >> 1;
-                        a[t] = L.Al[(ra + pp) * kLd + ra + p];
-                        b[t] = L.Bl[(cb + pp) * kLd + cb + p];
-                    }
-                    if (!factor4_cp(a, b, smin, f, pm2)) ok = 0;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const uint32_t e = (pm2 >> (2 * t)) & 3u;
-                        w[t] = e == 0u ? g[0] : e == 1u ? g[1] : e == 2u ? g[2] : g[3];
-                    }
-                    apply4(f, w);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (((pm2 >> (8 + 2 * t)) & 3u) == pos) yf = w[t];
-                }
-            }
-        } else {
-            yf = accf * (MULTI ? cn[0] : rdf);       // only 1x1 blocks finalise at this step
-        }
-        if (rf >= 0) {
-            vmax = fmax(vmax, fabs(yf));
-            L.R[c * kLd + rf] = yf;
+            yv[t] = v;
+            *(double *)(Rw + wof[t]) = v;
         }
         wave_sync_lds();
         // values of the blocks solved at step s, then the next step's operands
-        const double y0 = lds_at(Rc, Tc_.ty & 0xffffu), y1 = lds_at(Rc, Tc_.ty >> 16);
-        double z0[E], z1[E];
+        double y0[2], y1[2], z0[2], z1[2];
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            z0[i] = lds_at(Rb, (Tc_.tz[i] & 0xffffu) + 8 * (q + 4 * i));
-            z1[i] = lds_at(Rb, (Tc_.tz[i] >> 16) + 8 * (q + 4 * i));
+        for (int y = 0; y < 2; ++y) {
+            y0[y] = lds_at(Rb, cof[y] + (Tc_.col[y].y & 0xffffu));
+            y1[y] = lds_at(Rb, cof[y] + (Tc_.col[y].y >> 16));
         }
-        if constexpr (MULTI) {
-            // the inverse row of the entry above the one just finalised (used two or more steps on)
-            uint32_t ninf = 0u;
-            double nrd = 1.0;
 #pragma unroll
-            for (int i = 1; i < E; ++i)
-                if (fi == i) { ninf = info[i - 1]; nrd = rdd[i - 1]; }
-            if (fi > 0) fetch(ninf, nrd);
+        for (int x = 0; x < 2; ++x) {
+            z0[x] = lds_at(Rb, (Tc_.row[x].y & 0xffffu) + rof[x]);
+            z1[x] = lds_at(Rb, (Tc_.row[x].y >> 16) + rof[x]);
         }
         coefs(Tn, Cn);
         tables(s + 2, Tc_);
         __builtin_amdgcn_sched_barrier(0);
-        // contributions of the blocks solved at step s
+        // every value written is checked: its magnitude, and whether it is finite (a NaN, from
+        // two overflowing products of opposite sign, is invisible to the maximum; 0 times a
+        // non-finite value is NaN, times a finite one 0)
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            double v = acc[i];
-            v = fma(-Cc.a0[i], y0, v);
-            v = fma(-Cc.a1[i], y1, v);
-            v = fma(-z0[i], Cc.b0[i], v);
-            v = fma(-z1[i], Cc.b1[i], v);
-            acc[i] = v;
+        for (int t = 0; t < 4; ++t) vmax = fmax(vmax, fabs(yv[t]));
+        ynan = fma((yv[0] + yv[1]) + (yv[2] + yv[3]), 0.0, ynan);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int x = t & 1, y = t >> 1;
+            double v = acc[t];
+            v = fma(-Cc.a0[t], y0[y], v);
+            v = fma(-Cc.a1[t], y1[y], v);
+            v = fma(-z0[x], Cc.b0[t], v);
+            v = fma(-z1[x], Cc.b1[t], v);
+            acc[t] = v;
             vmax = fmax(vmax, fabs(v));
         }
     };
@@ -572,16 +528,25 @@ __device__ __forceinline__ int leaf_solve_t(LeafLds &L, int nr, int nc, double s
         step(s, TA, TB, CA, CB);
         if (s + 1 < steps) step(s + 1, TB, TA, CB, CA);
     }
+    if (ynan != 0.0) vmax = __builtin_inf();
     wave_sync_lds();
-    if (vmax_out) *vmax_out = vmax;
-    else if (!(vmax <= Tc)) ok = 0;
-    return ok;
+    if (zo0 >= 0) dz[zo0] = zv0;
+    if (zo1 >= 0) dz[zo1] = zv1;
+    wave_sync_lds();
+    if (vmax_out) {
+        *vmax_out = vmax;
+        return 1;
+    }
+    return vmax <= Tc ? 1 : 0;
 }
-__device__ __forceinline__ int leaf_solve(LeafLds &L, int nr, int nc, double smin, double Tc,
-                                          const LeafMasks &M, double *vmax_out = nullptr)
+__device__ __forceinline__ int leaf_solve(LeafLds &L, const LeafPatch &P, const LeafMasks &M, int nr, int nc,
+                                          double Tc, double *vmax_out = nullptr)
 {
-    if (M.m2 | M.n2) return leaf_solve_t<true>(L, nr, nc, smin, Tc, M, vmax_out);
-    return leaf_solve_t<false>(L, nr, nc, smin, Tc, M, vmax_out);
+    const int mode = (M.m2 ? 1 : 0) | (M.n2 ? 2 : 0);
+    if (mode == 3) return leaf_solve_t<3>(L, P, M, nr, nc, Tc, vmax_out);
+    if (mode == 1) return leaf_solve_t<1>(L, P, M, nr, nc, Tc, vmax_out);
+    if (mode == 2) return leaf_solve_t<2>(L, P, M, nr, nc, Tc, vmax_out);
+    return leaf_solve_t<0>(L, P, M, nr, nc, Tc, vmax_out);
 }
 
 }  // namespace trsyl

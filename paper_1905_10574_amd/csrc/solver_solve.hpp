@@ -270,8 +270,10 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             wave_sync_lds();
             if (li == 0) TRSYL_STAMP(stamp, 40 + 2 * d);
             const LeafMasks M = leaf_masks(LL, nr, ncl);
-            if (!leaf_setup(LL, M, smin)) ok = 0;
-            if (!leaf_solve(LL, nr, ncl, smin, Tc, M)) ok = 0;
+            const LeafPatch PT = leaf_setup(LL, M, smin);
+            if (li == 0 && d < 6) TRSYL_STAMP(stamp, 74 + d);
+            if (!PT.ok) ok = 0;
+            if (!leaf_solve(LL, PT, M, nr, ncl, Tc)) ok = 0;
             if (li == 0) TRSYL_STAMP(stamp, 41 + 2 * d);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -489,12 +491,13 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
             }
             wave_sync_lds();
             const LeafMasks M = leaf_masks(LL, nr, ncl);
-            if (!leaf_setup(LL, M, smin)) ok = 0;
+            const LeafPatch PT = leaf_setup(LL, M, smin);
+            if (!PT.ok) ok = 0;
             int t = 0;
             bool done = false, blind = false;
             for (int attempt = 0; attempt < 8 && uniform(__all(ok)); ++attempt) {
                 double vm;
-                if (!leaf_solve(LL, nr, ncl, smin, Tc, M, &vm)) ok = 0;
+                if (!leaf_solve(LL, PT, M, nr, ncl, Tc, &vm)) ok = 0;
                 vm = wave_max(vm);
                 if (vm <= Tc) {
                     // after a blind shift (the previous try overflowed), move the largest value

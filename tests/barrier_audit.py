@@ -126,11 +126,60 @@ def _restore(st, reg):
     return st[:i + 1] if st[i][0] == "mark" else st[:i]
 
 
-def transfer(insns, state, findings, where):
+def _halves(reg):
+    """'s[4:5]' -> ('s4', 's5'); None for anything else."""
+    m = re.match(r"^s\[(\d+):(\d+)\]$", reg)
+    if not m or int(m.group(2)) != int(m.group(1)) + 1:
+        return None
+    return f"s{m.group(1)}", f"s{m.group(2)}"
+
+
+def spill_slots(body):
+    """Lane slots of SGPR spills: (vgpr, lane) -> the set of SGPRs ever written there."""
+    slots = {}
+    for s in body:
+        parts = s.replace(",", " ").split()
+        if parts[0] == "v_writelane_b32" and len(parts) >= 4:
+            slots.setdefault((parts[1], parts[3]), set()).add(parts[2])
+    return slots
+
+
+def transfer(insns, state, findings, where, slots=None):
     st = tuple(state)
+    anded = {}      # this block: s_and_b64 dst, <saved exec>, x  ->  dst: the saved exec register
+    reread = {}     # this block: v_readlane_b32 sM, v, lane from a slot with one spilled SGPR
     for s in insns:
         parts = s.replace(",", " ").split()
         op = parts[0]
+        if op == "v_readlane_b32" and len(parts) >= 4 and slots is not None:
+            src = slots.get((parts[2], parts[3]), set())
+            if len(src) == 1:
+                reread[parts[1]] = next(iter(src))
+            else:
+                reread.pop(parts[1], None)
+            continue
+        if op == "s_and_b64" and len(parts) >= 4 and parts[1] != "exec":
+            for cand in (parts[2], parts[3]):
+                i = _find(st, cand)
+                if i >= 0 and st[i][0] == "mark":
+                    anded[parts[1]] = cand
+                    break
+            else:
+                anded.pop(parts[1], None)
+        if op == "s_or_b64" and len(parts) >= 4 and parts[1] == "exec" and parts[2] == "exec" \
+                and _find(st, parts[3]) < 0:
+            # exec restored from a copy that went through a spill slot: the saved register it was
+            # spilled from closes the region
+            h = _halves(parts[3])
+            if h and h[0] in reread and h[1] in reread:
+                lo, hi = reread[h[0]], reread[h[1]]
+                if lo.startswith("s") and hi.startswith("s") and lo[1:].isdigit() and hi[1:].isdigit() \
+                        and int(hi[1:]) == int(lo[1:]) + 1:
+                    parts = parts[:3] + [f"s[{lo[1:]}:{hi[1:]}]"]
+        if op == "s_mov_b64" and len(parts) >= 3 and parts[1] == "exec" and parts[2] in anded:
+            # exec = saved & cond: a region closed by restoring the saved register
+            st = _push(st, "narrow", anded[parts[2]])
+            continue
         if op == "s_barrier" or op.startswith("s_swappc") or op == "s_call_b64":
             narrowed = [r for k, r in st if k == "narrow"]
             if narrowed:
@@ -179,6 +228,7 @@ def audit(asm: str):
         bl = blocks(body)
         if not bl:
             continue
+        slots = spill_slots(body)
         index = {b[0]: i for i, b in enumerate(bl) if b[0]}
         succ = []
         for i, (lbl, insns, targets, fall) in enumerate(bl):
@@ -191,7 +241,7 @@ def audit(asm: str):
         work = [0]
         while work:
             i = work.pop()
-            out = transfer(bl[i][1], state_in[i], [], None)
+            out = transfer(bl[i][1], state_in[i], [], None, slots)
             for j in succ[i]:
                 new = _merge(state_in[j], out)
                 if new != state_in[j]:
@@ -199,5 +249,5 @@ def audit(asm: str):
                     work.append(j)
         for i, b in enumerate(bl):
             if state_in[i] is not None:
-                transfer(b[1], state_in[i], findings, (fname, b[0]))
+                transfer(b[1], state_in[i], findings, (fname, b[0]), slots)
     return [(w[0], w[1], s, regs) for (w, s, regs) in findings]
