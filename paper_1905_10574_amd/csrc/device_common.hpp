@@ -34,6 +34,16 @@ __device__ __forceinline__ double col(const double *M, int64_t ld, int64_t i, in
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
+// The lane index, opaque to the compiler: what is derived from it is computed where it is used
+// instead of being hoisted out of the enclosing loops, where it would hold registers (and spill)
+// for the whole loop.
+__device__ __forceinline__ int lane_here()
+{
+    int l = threadIdx.x & 63;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // --------------------------------------------------------------------------------------------
 // ProtectUpdate(c, a, y) (Sec. 2.1): for 0 <= c, a, y <= OMEGA, an s >= 0 with
 //     2^-s (c + a y) <= OMEGA.

@@ -84,6 +84,7 @@ __device__ __forceinline__ int64_t uni64(int64_t v)
 }
 template <class T> __device__ __forceinline__ T *uniptr(T *p) { return (T *)(uintptr_t)uni64((int64_t)(uintptr_t)p); }
 __device__ __forceinline__ int uni32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double unid(double v) { return __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, v))); }
 
 __device__ __forceinline__ Plan uniform_plan(const Plan &in)
 {

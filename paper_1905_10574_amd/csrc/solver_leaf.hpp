@@ -36,15 +36,21 @@ struct LeafLds {
     double R[17 * kLd];    // Y(r, k) at [k * 17 + r]: the right-hand side, then the solution
     double Al[17 * kLd];   // A_l(r, k) at [k * 17 + r]
     double Bl[17 * kLd + 1];   // B_l(r, k) at [k * 17 + r]; one zero after the last column
-    // Row 16 and column 16 of R, Al, Bl hold zeros.  Source tables, kTab entries each: entry
-    // 16 + k describes the k-th source block, every other entry points at the zero row / column.
-    uint2 tcol[kTab];   // k-th block row from the bottom, first row r0, second r1 (16 for 1x1):
-                        //   x = r0 * kSlab (a column of Al), y = r0 * 8 | r1 * 8 << 16 (rows of R)
-    uint2 trow[kTab];   // k-th block column from the left, first column c0, second c1:
-                        //   x = c0 * 8 (rows of a column of Bl), y = c0 * kSlab | c1 * kSlab << 16
-    uint8_t pr[2][8];   // row pairs: first and second row (16: none)
-    uint8_t pc[2][8];   // column pairs
+    // Row 16 and column 16 of R, Al, Bl hold zeros.
     double sink[64];    // per lane: where the values of patch entries outside the leaf go
+};
+
+// Block structure of one leaf of A_kk (its rows) or of B_ll (its columns), built once per tile.
+struct LeafShape {
+    uint32_t mask, two;   // bit i: a block starts at i; a 2x2 block starts at i
+    int n, nb;            // size, number of blocks
+    // Source table, kTab entries: entry 16 + k describes the k-th source block, every other entry
+    // points at the zero row / column.  Rows: k-th block row from the bottom, first row r0,
+    // second r1 (16 for 1x1): x = r0 * kSlab (a column of Al), y = r0 * 8 | r1 * 8 << 16 (rows of
+    // R).  Columns: k-th block column from the left, first column c0, second c1: x = c0 * 8 (rows
+    // of a column of Bl), y = c0 * kSlab | c1 * kSlab << 16.
+    uint2 tab[kTab];
+    uint8_t pair[2][8];   // pairs: first and second member (16: none)
 };
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -121,12 +127,10 @@ __device__ __forceinline__ void kron4(const double (&a)[4], const double (&b)[4]
 // P K Q = L U by elimination with complete pivoting, row swaps carried through the recorded
 // multipliers.  f[0..5]: l10 l20 l30 l21 l31 l32; f[6..11]: u01 u02 u03 u12 u13 u23;
 // f[12..15]: 1 / u_tt.  perm bits 2t: the position of row t, bits 8 + 2t: of column t.
-__device__ __forceinline__ bool factor4_cp(const double (&a)[4], const double (&b)[4], double smin,
-                                           double (&f)[16], uint32_t &perm)
+__device__ __forceinline__ bool factor4_cp(double (&K)[4][4], double smin, double (&f)[16], uint32_t &perm)
 {
-    double K[4][4], Lm[4][4];
+    double Lm[4][4];
     int pr[4] = {0, 1, 2, 3}, pc[4] = {0, 1, 2, 3};
-    kron4(a, b, K);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -175,14 +179,15 @@ __device__ __forceinline__ bool factor4_cp(const double (&a)[4], const double (&
         }
         if (fabs(K[t][t]) < smin) good = false;
         const double piv = good ? K[t][t] : 1.0;
+        const double rpiv = 1.0 / piv;
 #pragma unroll
         for (int i = t + 1; i < 4; ++i) {
-            const double l = K[i][t] / piv;
+            const double l = K[i][t] * rpiv;
             Lm[i][t] = l;
 #pragma unroll
             for (int j = t + 1; j < 4; ++j) K[i][j] = fma(-l, K[t][j], K[i][j]);
         }
-        f[12 + t] = 1.0 / piv;
+        f[12 + t] = rpiv;
     }
     f[0] = Lm[1][0]; f[1] = Lm[2][0]; f[2] = Lm[3][0]; f[3] = Lm[2][1]; f[4] = Lm[3][1]; f[5] = Lm[3][2];
     f[6] = K[0][1]; f[7] = K[0][2]; f[8] = K[0][3]; f[9] = K[1][2]; f[10] = K[1][3]; f[11] = K[2][3];
@@ -209,112 +214,122 @@ __device__ __forceinline__ void apply4(const double *f, double (&v)[4])
 }
 
 // ---------------------------------------------------------------------------------------------
-// Block structure of a leaf as bit masks (bit i: row / column i), from the subdiagonals.
+// Shape of a leaf of size n whose diagonal block starts at (o, o) of T (ld), by one wave: a
+// block starts at i unless T(o + i, o + i - 1) != 0.  Rows and columns are paired in the order
+// the pairs open: at a 2x2 block, and at every other 1x1 block.
 // ---------------------------------------------------------------------------------------------
-struct LeafMasks {
-    uint32_t rmask, cmask, m2, n2;   // first rows / columns of blocks, of 2x2 blocks
-    int na, nb;
-};
-__device__ __forceinline__ LeafMasks leaf_masks(const LeafLds &L, int nr, int nc)
+__device__ __forceinline__ void leaf_shape_wave(const double *T, int64_t ld, int o, int n, bool cols, LeafShape &S)
 {
-    const int lane = threadIdx.x & 63;
-    const bool rstart = (lane < nr) && (lane == 0 || L.Al[(lane - 1) * kLd + lane] == 0.0);
-    const bool cstart = (lane < nc) && (lane == 0 || L.Bl[(lane - 1) * kLd + lane] == 0.0);
-    LeafMasks M;
-    M.rmask = (uint32_t)__ballot(rstart);
-    M.cmask = (uint32_t)__ballot(cstart);
-    M.m2 = M.rmask & ~(M.rmask >> 1) & ((1u << (nr - 1)) - 1u);
-    M.n2 = M.cmask & ~(M.cmask >> 1) & ((1u << (nc - 1)) - 1u);
-    M.na = __popc(M.rmask);
-    M.nb = __popc(M.cmask);
-    return M;
+    const int lane = lane_here();
+    const bool start = lane < n && (lane == 0 || ldg(T + (int64_t)(o + lane - 1) * ld + o + lane) == 0.0);
+    const uint32_t mask = (uint32_t)__ballot(start);
+    const uint32_t two = mask & ~(mask >> 1) & ((1u << (n - 1)) - 1u);
+    const int nb = __popc(mask);
+    constexpr uint32_t zA = 16u * kSlab, zY = (16u * 8u) | ((16u * 8u) << 16);
+    constexpr uint32_t zB = 16u * 8u, zZ = (16u * kSlab) | ((16u * kSlab) << 16);
+    for (int t = lane; t < kTab; t += 64) S.tab[t] = cols ? make_uint2(zB, zZ) : make_uint2(zA, zY);
+    if (lane < 16) (&S.pair[0][0])[lane] = 16;
+    if (lane == 0) {
+        S.mask = mask;
+        S.two = two;
+        S.n = n;
+        S.nb = nb;
+    }
+    wave_sync_lds();
+    if (lane < 16 && ((mask >> lane) & 1u)) {
+        const int r = lane;
+        const uint32_t one = mask & ~two, below = (1u << r) - 1u;
+        const int n2b = __popc(two & below), k1 = __popc(one & below);
+        const bool is2 = (two >> r) & 1u;
+        const uint32_t r1 = is2 ? (uint32_t)r + 1u : 16u;
+        if (!cols)
+            S.tab[16 + nb - 1 - __popc(mask & below)] =
+                make_uint2((uint32_t)r * kSlab, ((uint32_t)r * 8u) | ((r1 * 8u) << 16));
+        else
+            S.tab[16 + __popc(mask & below)] =
+                make_uint2((uint32_t)r * 8u, ((uint32_t)r * kSlab) | ((r1 * kSlab) << 16));
+        if (is2) {
+            const int pi = n2b + ((k1 + 1) >> 1);
+            S.pair[0][pi] = (uint8_t)r;
+            S.pair[1][pi] = (uint8_t)(r + 1);
+        } else if (!(k1 & 1)) {
+            S.pair[0][n2b + (k1 >> 1)] = (uint8_t)r;
+        } else {
+            const int rp = 31 - __clz(one & below);    // the 1x1 block that opened this pair
+            S.pair[1][__popc(two & ((1u << rp) - 1u)) + ((k1 - 1) >> 1)] = (uint8_t)r;
+        }
+    }
+    wave_sync_lds();
 }
 
 // ---------------------------------------------------------------------------------------------
 // The lane's patch: rows r[x] and columns c[y] of its four entries t = x + 2 y (16: none), and
-// W, the inverse of every block system inside the patch (zero elsewhere).  ok = 0 when a pivot
-// of those systems fell below smin.
+// W, the inverse of every block system inside the patch (zero elsewhere), its rows in the order
+// perm gives (the rows come out in the factorisation's column order, which the sweep undoes by
+// where it writes each value).  ok = 0 when a pivot of those systems fell below smin.
 // ---------------------------------------------------------------------------------------------
 struct LeafPatch {
     int r[2], c[2];
     double w[4][4];
+    uint32_t perm;   // row t of W gives the unknown of entry (perm >> 2 t) & 3
     int ok;
 };
 
-// Per-leaf set-up by its wave: row / column pairs (lanes 0..15 one row each, lanes 16..31 one
-// column each), the source tables, then every lane's patch and block inverses.
-__device__ __forceinline__ LeafPatch leaf_setup(LeafLds &L, const LeafMasks &M, double smin)
+// Every lane factors one 4 x 4 system, K = I (x) A_p + B_p^T (x) I over its patch, where A_p
+// (B_p) is the 2x2 block of its row (column) pair when the pair is a 2x2 block and the pair's
+// diagonal otherwise: K then falls apart into the patch's 1-, 2- and 4-unknown systems of
+// Sec. 2.1, which elimination with complete pivoting factors independently (the coupling
+// between them is exactly zero).  An entry outside the leaf gets a row and column of its own with
+// pivot 2 smin.  A leaf without 2x2 blocks takes the reciprocals of the 1x1 systems directly.
+__device__ __forceinline__ LeafPatch leaf_setup(LeafLds &L, const LeafShape &RS, const LeafShape &CS, double smin)
 {
-    const int lane = threadIdx.x & 63;
-    constexpr uint32_t zA = 16u * kSlab, zY = (16u * 8u) | ((16u * 8u) << 16);
-    constexpr uint32_t zB = 16u * 8u, zZ = (16u * kSlab) | ((16u * kSlab) << 16);
-    for (int t = lane; t < kTab; t += 64) {
-        L.tcol[t] = make_uint2(zA, zY);
-        L.trow[t] = make_uint2(zB, zZ);
-    }
-    if (lane < 16) (&L.pr[0][0])[lane] = 16;
-    else if (lane < 32) (&L.pc[0][0])[lane - 16] = 16;
+    const int lane = lane_here();
     if (lane == 0) L.Bl[17 * kLd] = 0.0;
-    wave_sync_lds();
-    if (lane < 32) {
-        const bool isC = lane >= 16;
-        const int r = lane & 15;
-        const uint32_t mask = isC ? M.cmask : M.rmask, two = isC ? M.n2 : M.m2;
-        const uint32_t one = mask & ~two;
-        if ((mask >> r) & 1u) {
-            const uint32_t below = (1u << r) - 1u;
-            const int n2b = __popc(two & below), k1 = __popc(one & below);
-            const bool is2 = (two >> r) & 1u;
-            const uint32_t r1 = is2 ? (uint32_t)r + 1u : 16u;
-            if (!isC) {
-                const int k = M.na - 1 - __popc(mask & below);
-                L.tcol[16 + k] = make_uint2((uint32_t)r * kSlab, ((uint32_t)r * 8u) | ((r1 * 8u) << 16));
-            } else {
-                const int k = __popc(mask & below);
-                L.trow[16 + k] = make_uint2((uint32_t)r * 8u, ((uint32_t)r * kSlab) | ((r1 * kSlab) << 16));
-            }
-            // pairs are numbered in the order they open: at a 2x2 block, and at every other 1x1
-            uint8_t (*Pr)[8] = isC ? L.pc : L.pr;
-            if (is2) {
-                const int pi = n2b + ((k1 + 1) >> 1);
-                Pr[0][pi] = (uint8_t)r;
-                Pr[1][pi] = (uint8_t)(r + 1);
-            } else if (!(k1 & 1)) {
-                Pr[0][n2b + (k1 >> 1)] = (uint8_t)r;
-            } else {
-                const int rp = 31 - __clz(one & below);    // the 1x1 block that opened this pair
-                Pr[1][__popc(two & ((1u << rp) - 1u)) + ((k1 - 1) >> 1)] = (uint8_t)r;
-            }
-        }
-    }
-    wave_sync_lds();
     LeafPatch P;
     const int rho = lane & 7, kap = lane >> 3;
-    P.r[0] = L.pr[0][rho];
-    P.r[1] = L.pr[1][rho];
-    P.c[0] = L.pc[0][kap];
-    P.c[1] = L.pc[1][kap];
+    P.r[0] = RS.pair[0][rho];
+    P.r[1] = RS.pair[1][rho];
+    P.c[0] = CS.pair[0][kap];
+    P.c[1] = CS.pair[1][kap];
+    const int ra = P.r[0], rb = P.r[1], ca = P.c[0], cb = P.c[1];
+    // the patch's diagonal blocks (row / column 16 of the buffers hold zeros)
+    const double a00 = L.Al[ra * kLd + ra], a11 = L.Al[rb * kLd + rb];
+    const double b00 = L.Bl[ca * kLd + ca], b11 = L.Bl[cb * kLd + cb];
+    bool pad[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) pad[t] = P.r[t & 1] >= 16 || P.c[t >> 1] >= 16;
+    int ok = 1;
+    P.perm = 0xE4u;                                     // rows in entry order
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) P.w[i][j] = 0.0;
-    int ok = 1;
-    const int ra = P.r[0], ca = P.c[0];
-    const bool R2 = ra < 16 && ((M.m2 >> ra) & 1u);
-    const bool C2 = ca < 16 && ((M.n2 >> ca) & 1u);
-    if (R2 && C2) {
-        // 4 unknowns (Sec. 2.1's Kronecker system of a 2x2 block pair), position t = x + 2 y
-        double a[4], b[4], f[16];
-        uint32_t pm;
+    if (uniform((RS.two | CS.two) ? 1 : 0) == 0) {
+        const double d[4] = {a00 + b00, a11 + b00, a00 + b11, a11 + b11};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int p = t & 1, pp = t >> 1;
-            a[t] = L.Al[(ra + pp) * kLd + ra + p];
-            b[t] = L.Bl[(ca + pp) * kLd + ca + p];
+            if (!pad[t] && !(fabs(d[t]) >= smin)) ok = 0;
+            P.w[t][t] = pad[t] ? 0.0 : 1.0 / d[t];
         }
-        if (!factor4_cp(a, b, smin, f, pm)) ok = 0;
-        // column j of the inverse: e_j in the factorisation's row order, the unknowns come back
-        // in its column order
+    } else {
+        const bool R2 = ra < 16 && ((RS.two >> ra) & 1u);
+        const bool C2 = ca < 16 && ((CS.two >> ca) & 1u);
+        const double a10 = R2 ? L.Al[ra * kLd + rb] : 0.0, a01 = R2 ? L.Al[rb * kLd + ra] : 0.0;
+        const double b10 = C2 ? L.Bl[ca * kLd + cb] : 0.0, b01 = C2 ? L.Bl[cb * kLd + ca] : 0.0;
+        const double a[4] = {a00, a10, a01, a11}, b[4] = {b00, b10, b01, b11};
+        double K[4][4];
+        kron4(a, b, K);
+        const double pv = 2.0 * smin;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (pad[i] || pad[j]) K[i][j] = i == j ? pv : 0.0;
+        double f[16];
+        uint32_t pm;
+        if (!factor4_cp(K, smin, f, pm)) ok = 0;
+        // column j of the inverse: e_j in the factorisation's row order; the unknowns come back
+        // in its column order, kept as the row order of W
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             double v[4];
@@ -322,84 +337,31 @@ __device__ __forceinline__ LeafPatch leaf_setup(LeafLds &L, const LeafMasks &M, 
             for (int t = 0; t < 4; ++t) v[t] = ((pm >> (2 * t)) & 3u) == (uint32_t)j ? 1.0 : 0.0;
             apply4(f, v);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t u = (pm >> (8 + 2 * t)) & 3u;
-#pragma unroll
-                for (int uu = 0; uu < 4; ++uu)
-                    if (u == (uint32_t)uu) P.w[uu][j] = v[t];
-            }
+            for (int t = 0; t < 4; ++t) P.w[t][j] = v[t];
         }
-    } else if (R2) {
-        // (A11 + b_cc I) z = g over the block's two rows, for each column of the patch
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-            const int c = P.c[y];
-            if (c < 16) {
-                const double bcc = L.Bl[c * kLd + c];
-                Factor2 F;
-                if (!factor2_cp(L.Al[ra * kLd + ra] + bcc, L.Al[(ra + 1) * kLd + ra], L.Al[ra * kLd + ra + 1],
-                                L.Al[(ra + 1) * kLd + ra + 1] + bcc, smin, F))
-                    ok = 0;
-                double x00 = 1.0, x10 = 0.0, x01 = 0.0, x11 = 1.0;
-                apply2(F, x00, x10);
-                apply2(F, x01, x11);
-                P.w[2 * y][2 * y] = x00;
-                P.w[2 * y][2 * y + 1] = x01;
-                P.w[2 * y + 1][2 * y] = x10;
-                P.w[2 * y + 1][2 * y + 1] = x11;
-            }
-        }
-    } else if (C2) {
-        // z (a_rr I + B11) = g over the block's two columns, for each row of the patch
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            const int r = P.r[x];
-            if (r < 16) {
-                const double arr = L.Al[r * kLd + r];
-                Factor2 F;
-                if (!factor2_cp(arr + L.Bl[ca * kLd + ca], L.Bl[ca * kLd + ca + 1], L.Bl[(ca + 1) * kLd + ca],
-                                arr + L.Bl[(ca + 1) * kLd + ca + 1], smin, F))
-                    ok = 0;
-                double x00 = 1.0, x10 = 0.0, x01 = 0.0, x11 = 1.0;
-                apply2(F, x00, x10);
-                apply2(F, x01, x11);
-                P.w[x][x] = x00;
-                P.w[x][x + 2] = x01;
-                P.w[x + 2][x] = x10;
-                P.w[x + 2][x + 2] = x11;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int r = P.r[t & 1], c = P.c[t >> 1];
-            if (r < 16 && c < 16) {
-                const double d = L.Al[r * kLd + r] + L.Bl[c * kLd + c];
-                if (fabs(d) < smin) ok = 0;
-                P.w[t][t] = 1.0 / d;
-            }
-        }
+        P.perm = (pm >> 8) & 0xFFu;
     }
     P.ok = ok;
     return P;
 }
 
 // ---------------------------------------------------------------------------------------------
-// The sweep.  MODE bit 0: the leaf has 2x2 blocks of A_l, bit 1: of B_l (W's coupling pattern).
+// The sweep.  MODE 1: W is a general 4 x 4 (rows in perm order), MODE 0: W is diagonal.
 // Returns 0 when a value it produced (a right-hand side after an update, or a value written)
 // exceeded Tc or was not finite; with vmax_out the largest magnitude (infinity for a non-finite
 // value) is stored there instead and 1 is returned.
 // ---------------------------------------------------------------------------------------------
 template <int MODE>
-__device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, const LeafMasks &M, int nr, int nc,
+__device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, const LeafShape &RS, const LeafShape &CS,
+                                            int nr, int nc,
                                             double Tc, double *vmax_out)
 {
-    const int lane = threadIdx.x & 63;
-    const int steps = M.na + M.nb - 1;
+    const int lane = lane_here();
+    const int steps = RS.nb + CS.nb - 1;
     // set the diagonal blocks of A_l (lanes 0..15, row r) and B_l (lanes 16..31, column c) to
     // zero for the sweep; the lane keeps the values it cleared
     double *dz = lane < 16 ? L.Al : L.Bl;
-    const uint32_t dtwo = lane < 16 ? M.m2 : M.n2;
+    const uint32_t dtwo = lane < 16 ? RS.two : CS.two;
     const int di = lane & 15;
     int zo0 = -1, zo1 = -1;
     double zv0 = 0.0, zv1 = 0.0;
@@ -420,25 +382,27 @@ __device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, cons
         const int r = P.r[x];
         rof[x] = (uint32_t)r * 8u;
         rtab[x] = kTabIdle;
-        if (r < 16) rtab[x] = 16 - (M.na - 1 - (__popc(M.rmask & ((2u << r) - 1u)) - 1));
+        if (r < 16) rtab[x] = 16 - (RS.nb - 1 - (__popc(RS.mask & ((2u << r) - 1u)) - 1));
     }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
         const int c = P.c[y];
         cof[y] = (uint32_t)c * kSlab;
         ctab[y] = kTabIdle;
-        if (c < 16) ctab[y] = 16 - (__popc(M.cmask & ((2u << c) - 1u)) - 1);
+        if (c < 16) ctab[y] = 16 - (__popc(CS.mask & ((2u << c) - 1u)) - 1);
     }
     wave_sync_lds();
     const char *Rb = (const char *)L.R, *Ab = (const char *)L.Al, *Bb = (const char *)L.Bl;
     char *Rw = (char *)L.R;
     double acc[4];
-    uint32_t wof[4];     // where entry t's value is written: its place in R, or the lane's sink
+    uint32_t wof[4];     // where row t of W x (right-hand sides) goes: its entry's place in R,
+                         // or the lane's sink for an entry outside the leaf
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         acc[t] = lds_at(Rb, cof[t >> 1] + rof[t & 1]);
-        const bool real = P.r[t & 1] < 16 && P.c[t >> 1] < 16;
-        wof[t] = real ? cof[t >> 1] + rof[t & 1] : (uint32_t)((const char *)&L.sink[lane] - Rb);
+        const uint32_t u = (P.perm >> (2 * t)) & 3u;
+        const bool real = P.r[u & 1] < 16 && P.c[u >> 1] < 16;
+        wof[t] = real ? cof[u >> 1] + rof[u & 1] : (uint32_t)((const char *)&L.sink[lane] - Rb);
     }
     double vmax = 0.0;
     // software pipeline: the tables of step s + 2 and the coefficients of step s + 1 are read
@@ -447,9 +411,9 @@ __device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, cons
     struct Coef { double a0[4], a1[4], b0[4], b1[4]; };
     auto tables = [&](int s, Tabs &T) {
 #pragma unroll
-        for (int y = 0; y < 2; ++y) T.col[y] = L.tcol[ctab[y] + s];
+        for (int y = 0; y < 2; ++y) T.col[y] = RS.tab[ctab[y] + s];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) T.row[x] = L.trow[rtab[x] + s];
+        for (int x = 0; x < 2; ++x) T.row[x] = CS.tab[rtab[x] + s];
     };
     auto coefs = [&](const Tabs &T, Coef &C) {
 #pragma unroll
@@ -470,15 +434,11 @@ __device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, cons
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             double v;
-            if constexpr (MODE == 3) {
+            if constexpr (MODE == 1) {
                 v = P.w[t][0] * acc[0];
                 v = fma(P.w[t][1], acc[1], v);
                 v = fma(P.w[t][2], acc[2], v);
                 v = fma(P.w[t][3], acc[3], v);
-            } else if constexpr (MODE == 1) {
-                v = fma(P.w[t][t | 1], acc[t | 1], P.w[t][t & 2] * acc[t & 2]);
-            } else if constexpr (MODE == 2) {
-                v = fma(P.w[t][(t & 1) + 2], acc[(t & 1) + 2], P.w[t][t & 1] * acc[t & 1]);
             } else {
                 v = P.w[t][t] * acc[t];
             }
@@ -539,14 +499,13 @@ __device__ __forceinline__ int leaf_solve_t(LeafLds &L, const LeafPatch &P, cons
     }
     return vmax <= Tc ? 1 : 0;
 }
-__device__ __forceinline__ int leaf_solve(LeafLds &L, const LeafPatch &P, const LeafMasks &M, int nr, int nc,
-                                          double Tc, double *vmax_out = nullptr)
+__device__ __forceinline__ int leaf_solve(LeafLds &L, const LeafPatch &P, const LeafShape &RS, const LeafShape &CS,
+                                          int nr, int nc, double Tc, double *vmax_out = nullptr)
 {
-    const int mode = (M.m2 ? 1 : 0) | (M.n2 ? 2 : 0);
-    if (mode == 3) return leaf_solve_t<3>(L, P, M, nr, nc, Tc, vmax_out);
-    if (mode == 1) return leaf_solve_t<1>(L, P, M, nr, nc, Tc, vmax_out);
-    if (mode == 2) return leaf_solve_t<2>(L, P, M, nr, nc, Tc, vmax_out);
-    return leaf_solve_t<0>(L, P, M, nr, nc, Tc, vmax_out);
+    // with any 2x2 block, W comes from 4 x 4 factorisations whose pivoting may order its rows
+    // freely: the full product; without, W is diagonal
+    if (uniform((RS.two | CS.two) ? 1 : 0)) return leaf_solve_t<1>(L, P, RS, CS, nr, nc, Tc, vmax_out);
+    return leaf_solve_t<0>(L, P, RS, CS, nr, nc, Tc, vmax_out);
 }
 
 }  // namespace trsyl

@@ -39,6 +39,7 @@ constexpr int kMaxParts = kMaxLeaves > kWaves ? kMaxLeaves : kWaves;
 
 struct SolveLds {
     LeafLds leaf[kWaves];
+    LeafShape rs[kMaxLeaves], cs[kMaxLeaves];   // shapes of the tile's row and column leaves
     double part[kMaxParts][16 * kLd];   // split-K partial sums of the leaf GEMMs
     int la[kMaxLeaves + 1], lb[kMaxLeaves + 1];
     int nla, nlb;
@@ -90,6 +91,18 @@ __device__ inline void leaf_offsets_wave(const double *Ad, int64_t lda, int mr, 
     if (lane == 32) { lb[0] = 0; lb[nb] = nc; *nlb = nb; }
 }
 
+// The shapes of every row leaf (of A_kk) and column leaf (of B_ll), one wave per leaf, ready
+// after the closing barrier.
+__device__ inline void leaf_shapes(const Plan &P, const double *Ad, const double *Bd, SolveLds &L, int nla, int nlb)
+{
+    const int w = uniform((int)(threadIdx.x >> 6));
+    for (int I = w; I < nla; I += kWaves)
+        leaf_shape_wave(Ad, P.lda, L.la[I], L.la[I + 1] - L.la[I], false, L.rs[I]);
+    for (int J = w; J < nlb; J += kWaves)
+        leaf_shape_wave(Bd, P.ldb, L.lb[J], L.lb[J + 1] - L.lb[J], true, L.cs[J]);
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------------------------
 // One wave accumulates acc += Aop(0:nr, k) Bop(k, 0:ncl) over k in [k0, k1), 32 k at a time, the
 // next 32-k chunk's operands in flight while the current chunk's MFMAs run.  Lane (r, q) holds
@@ -99,7 +112,7 @@ __device__ inline void leaf_offsets_wave(const double *Ad, int64_t lda, int mr, 
 __device__ __forceinline__ void leaf_gemm(d4 &acc, const double *Aop, int64_t lda, int nr,
                                           const double *Bop, int64_t ldb, int ncl, int k0, int k1)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_here();
     const int r = lane & 15, q = lane >> 4;
     if (k0 >= k1) return;
     const bool va = r < nr, vb = r < ncl;
@@ -153,7 +166,7 @@ __device__ __forceinline__ void leaf_inputs(const Plan &P, const double *Ad, con
                                             const DevView &Y, const SolveLds &L, LeafLds &LL,
                                             int I, int J, double (&rhs)[4])
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_here();
     const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
     const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
 #pragma unroll
@@ -210,6 +223,7 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
     }
     __syncthreads();
     const int nla = uniform(L.nla), nlb = uniform(L.nlb);
+    leaf_shapes(P, Ad, Bd, L, nla, nlb);
     const int64_t lds = mr;
     LeafLds &LL = L.leaf[w];
     int ok = 1;
@@ -255,6 +269,7 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             if (li >= kWaves) leaf_inputs(P, Ad, Bd, Y, L, LL, I, J, rhs);
             const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
             const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+            const int lane = lane_here();
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int mm = lane & 15, nn = (lane >> 4) + 4 * i;
@@ -269,11 +284,10 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             }
             wave_sync_lds();
             if (li == 0) TRSYL_STAMP(stamp, 40 + 2 * d);
-            const LeafMasks M = leaf_masks(LL, nr, ncl);
-            const LeafPatch PT = leaf_setup(LL, M, smin);
+            const LeafPatch PT = leaf_setup(LL, L.rs[I], L.cs[J], smin);
             if (li == 0 && d < 6) TRSYL_STAMP(stamp, 74 + d);
             if (!PT.ok) ok = 0;
-            if (!leaf_solve(LL, PT, M, nr, ncl, Tc)) ok = 0;
+            if (!leaf_solve(LL, PT, L.rs[I], L.cs[J], nr, ncl, Tc)) ok = 0;
             if (li == 0) TRSYL_STAMP(stamp, 41 + 2 * d);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -414,6 +428,7 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
     }
     __syncthreads();
     const int nla = uniform(L.nla), nlb = uniform(L.nlb);
+    leaf_shapes(P, Ad, Bd, L, nla, nlb);
     for (int r = threadIdx.x; r < mr; r += kThreads) {
         int I = 0;
         while (L.la[I + 1] <= r) ++I;
@@ -490,14 +505,13 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
                 LL.R[nn * kLd + mm] = v[i];
             }
             wave_sync_lds();
-            const LeafMasks M = leaf_masks(LL, nr, ncl);
-            const LeafPatch PT = leaf_setup(LL, M, smin);
+            const LeafPatch PT = leaf_setup(LL, L.rs[I], L.cs[J], smin);
             if (!PT.ok) ok = 0;
             int t = 0;
             bool done = false, blind = false;
             for (int attempt = 0; attempt < 8 && uniform(__all(ok)); ++attempt) {
                 double vm;
-                if (!leaf_solve(LL, PT, M, nr, ncl, Tc, &vm)) ok = 0;
+                if (!leaf_solve(LL, PT, L.rs[I], L.cs[J], nr, ncl, Tc, &vm)) ok = 0;
                 vm = wave_max(vm);
                 if (vm <= Tc) {
                     // after a blind shift (the previous try overflowed), move the largest value
@@ -783,12 +797,15 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         const double *Ad = P.A + (int64_t)r0 * P.lda + r0;
         const double *Bd = P.B + (int64_t)c0 * P.ldb + c0;
         double *Y = P.C + (int64_t)c0 * P.ldc + r0;
+        // the pivot floor and the certificate's bound are the same in every lane: kept in
+        // scalar registers
         double smin = 0x1p-52 * (*P.gmax);
         if (smin < 0x1p-1022) smin = 0x1p-1022;
+        smin = unid(smin);
         const double dA = P.anorm[(size_t)ti * P.pt + ti];
         const double dB = P.bnorm[(size_t)tl * P.qt + tl];
         const double dB1 = P.bdiag1[tl];
-        const double Tc = kOmega / (64.0 + 8.0 * (dA + dB1 + dB));
+        const double Tc = unid(kOmega / (64.0 + 8.0 * (dA + dB1 + dB)));
         const DevView vY = dev_view(Y, P.ldc, mr, nc);
         int done = 0;
         // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
