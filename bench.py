@@ -166,11 +166,70 @@ def critical_path(T, L, opts, m, n, Ac, Bc, C0, dev):
     on_path = float(sum(s_end[x] - s_start[x] for x in chain) / 1e5)
     span = float((s_end[chain[-1]] - s_start[chain[0]]) / 1e5)
     floor_ms = W.flop_count(m, n) / (PEAK_FP64_TF * 1e12) * 1e3
+    upd = kind != 0
     return {"tile_solve_us": round(tk2, 2), "solves_on_path": len(chain),
             "solve_ms_on_path": round(on_path, 3), "path_ms": round(span, 3),
             "update_links_ms": round(span - on_path, 3),
             "bound_ms": round(max(floor_ms, (pt + qt - 1) * tk2 / 1e3), 3),
-            "mfma_floor_ms": round(floor_ms, 3)}
+            "mfma_floor_ms": round(floor_ms, 3),
+            # workgroup time summed over tasks, by kind (the run's time split)
+            "solve_tasks_wg_ms": round(float((t1[sol] - t0[sol]).sum()) / 1e5, 3),
+            "update_tasks_wg_ms": round(float((t1[upd] - t0[upd]).sum()) / 1e5, 3),
+            "tile_update_us": round(float(np.mean((t1[upd] - t0[upd]) / 100.0)), 2) if upd.any() else None}
+
+
+def growth_record(T, L, dev, seed: int, reps: int = 3):
+    """The growth workload (m = n = 4096: all 1x1 blocks, lambda_A U[-1,1] 1e-2, |lambda_A +
+    lambda_B| in [1e-3, 1e-2] on the paired diagonal, strict upper parts U[-10,10], C U[-1,1]):
+    median of `reps` timed solves after one warm-up (stream-synchronised, host clock), the
+    scaling events the library counted, and the time split of one traced solve (workgroup time in
+    tile solves and tile updates, and the critical chain of tile solves) -- Sec. 4's cost of
+    robustness on the input where every tile scales."""
+    import statistics
+    import torch
+    import trsyl_workloads as W
+    m = 4096
+    print(f"[bench] growth workload m=n={m}: generating", file=sys.stderr, flush=True)
+    A_np, B_np, C_np = W.config_growth(seed, m, m)
+    Ac, Bc, C0 = T.colmajor(A_np, dev), T.colmajor(B_np, dev), T.colmajor(C_np, dev)
+    del A_np, B_np, C_np
+    opts = T.make_opts()
+    ws = T.workspace_size(m, m, opts)
+    keep, ptr = T._aligned_workspace(ws, dev)
+    cnt = torch.zeros(4, dtype=torch.int32, device=dev)
+    e_t = torch.zeros(1, dtype=torch.int64, device=dev)
+    sc_t = torch.zeros(1, dtype=torch.float64, device=dev)
+    info_t = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    times, Yc = [], None
+    for rep in range(1 + reps):
+        Yc = C0.clone()
+        cnt.zero_()
+        opts.counters = cnt.data_ptr()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        rc = L.trsyl_robust(m, m, Ac.data_ptr(), m, Bc.data_ptr(), m, Yc.data_ptr(), m, e_t.data_ptr(),
+                            sc_t.data_ptr(), info_t.data_ptr(), ctypes.byref(opts), ptr, ws, stream)
+        if rc != 0:
+            raise RuntimeError(f"trsyl_robust returned {rc}")
+        torch.cuda.synchronize(dev)
+        if rep > 0:
+            times.append(time.perf_counter() - t0)
+    opts.counters = None
+    c = cnt.cpu().tolist()
+    t = statistics.median(times)
+    resid = residual_lib(T, Ac, Bc, Yc, e_t, C0, m, m)
+    split = critical_path(T, L, opts, m, m, Ac, Bc, C0, dev)
+    pt = (m + opts.tile_m - 1) // opts.tile_m
+    print(f"[bench] growth: {1e3 * t:.2f} ms, e={int(e_t.item())}, events {c[:3]}", file=sys.stderr, flush=True)
+    return {"workload": "growth m=n=4096: lambda_A U[-1,1]*1e-2, |lambda_A+lambda_B| in [1e-3,1e-2], "
+                        "strict upper U[-10,10], C U[-1,1], seed %d" % seed,
+            "tile": opts.tile_m, "ms_median": round(1e3 * t, 3), "reps": reps,
+            "gflops": round(W.flop_count(m, m) / t / 1e9, 2), "scale_log2": int(e_t.item()),
+            "info": int(info_t.item()), "residual_eq9": resid,
+            "events": {"tile_solves": pt * pt, "leaf_tiled_tile_solves": c[2], "fallback_tile_solves": c[0],
+                       "tile_updates": pt * pt * (pt - 1), "scaled_tile_updates": c[1]},
+            "time_split": split}
 
 
 def paper_sweeps(args):
@@ -370,6 +429,7 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the FP32+refine measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the eq. (9) residual check")
+    ap.add_argument("--no-growth", action="store_true", help="skip the growth-workload record")
     ap.add_argument("--paper", action="store_true",
                     help="run the paper's experiment workloads instead (Sec. 3 test matrices, Sec. 4 experiments): mu = m, "
                          "nu = n at the --paper-sizes, then the cost-of-robustness sweep nu = 1e-2, "
@@ -527,6 +587,8 @@ def main():
                           "and residual in FP64; a sweep begins with an FP64 eq. (9) check (~F flops) and, "
                           "above refine_tol, adds an FP32-update correction solve"}
 
+    growth = None if args.no_growth else growth_record(T, L, dev, args.seed)
+
     cpu = None
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
@@ -561,6 +623,7 @@ def main():
         "cpu_baseline": cpu,
         "critical_path": cpath,
         "fp32_refine": refine,
+        "growth": growth,
         "residual_eq9": resid,
         "scale_log2": e,
         "info": info,

@@ -44,6 +44,7 @@ struct SolveLds {
     int la[kMaxLeaves + 1], lb[kMaxLeaves + 1];
     int nla, nlb;
     int fail;
+    int tguess, tnext;   // leaf-tiled solve: growth shift to start from, and this front's largest
     union {
         struct {   // Algorithm 2 on the whole tile
             int as[kMaxTile + 1], bs[kMaxTile + 1];
@@ -328,26 +329,22 @@ __device__ __forceinline__ void lds_max_nonneg(double *p, double v)
     atomicMax((unsigned long long *)p, (unsigned long long)__double_as_longlong(v));
 }
 
-// Row-sum norms of the leaf blocks of an mr x nc matrix (thread r sums row r; columns c >= c_lo(r)),
-// max-reduced per (row leaf, column leaf) into out[I * kML + J].  X(r, c) = get(r, c).
+// Row-sum norms of the leaf blocks of a rows x cols matrix (only columns c >= r - 1 of row r when
+// upper), max-reduced per (row leaf, column leaf) into out[I * kML + J].  Thread t takes the
+// (row, column leaf) items t, t + kThreads, ... with the row running fastest, so a column's rows
+// are read by consecutive threads; X(r, c) = get(r, c).
 template <class Get>
 __device__ __forceinline__ void leaf_block_norms(int rows, int cols, bool upper, const uint8_t *rleaf,
-                                                 const int *cb, double *out, Get get)
+                                                 const int *cb, int ncb, double *out, Get get)
 {
-    for (int r = threadIdx.x; r < rows; r += kThreads) {
-        const int I = rleaf[r];
-        int c = upper && r > 0 ? r - 1 : 0;
-        int J = 0;
-        while (cb[J + 1] <= c) ++J;
+    for (int it = threadIdx.x; it < rows * ncb; it += kThreads) {
+        const int r = it % rows, J = it / rows;
+        int c = cb[J];
+        const int c1 = cb[J + 1] < cols ? cb[J + 1] : cols;
+        if (upper && c < r - 1) c = r - 1;
         double s = 0.0;
-        for (; c < cols; ++c) {
-            s += fabs(get(r, c));
-            if (c + 1 == cb[J + 1]) {
-                lds_max_nonneg(&out[I * kML + J], s);
-                s = 0.0;
-                ++J;
-            }
-        }
+        for (; c < c1; ++c) s += fabs(get(r, c));
+        lds_max_nonneg(&out[rleaf[r] * kML + J], s);
     }
 }
 
@@ -407,12 +404,17 @@ __device__ __forceinline__ void leaf_gemm_scaled(d4 &acc, const double *Aop, int
 }
 
 __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *Bd, const DevView &Y,
-                                 double *S, int mr_, int nc_, double smin, double Tc, SolveLds &L)
+                                 double *S, int mr_, int nc_, double smin, double Tc, SolveLds &L,
+                                 uint64_t *stamp)
 {
     const int mr = uniform(mr_), nc = uniform(nc_);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (w == 0) leaf_offsets_wave(Ad, P.lda, mr, Bd, P.ldb, nc, L.la, L.lb, &L.nla, &L.nlb);
-    if (threadIdx.x == 0) L.fail = 0;
+    if (threadIdx.x == 0) {
+        L.fail = 0;
+        L.tguess = 0;
+        L.tnext = 0;
+    }
     if (lane < 33) {                                 // zero row / column 16 of the leaf buffers
         const int o = lane < 17 ? lane * kLd + 16 : 16 * kLd + (lane - 17);
         L.leaf[w].R[o] = 0.0;
@@ -440,11 +442,11 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
         L.colleaf[c] = (uint8_t)J;
     }
     __syncthreads();
-    leaf_block_norms(mr, nc, false, L.rowleaf, L.lb, L.nC,
+    leaf_block_norms(mr, nc, false, L.rowleaf, L.lb, nlb, L.nC,
                      [&](int r, int c) { return ld_dev(Y, (int64_t)c * P.ldc + r); });
-    leaf_block_norms(mr, mr, true, L.rowleaf, L.la, L.aN,
+    leaf_block_norms(mr, mr, true, L.rowleaf, L.la, nla, L.aN,
                      [&](int r, int c) { return ldg(Ad + (int64_t)c * P.lda + r); });
-    leaf_block_norms(nc, nc, true, L.colleaf, L.lb, L.bN,
+    leaf_block_norms(nc, nc, true, L.colleaf, L.lb, nlb, L.bN,
                      [&](int r, int c) { return ldg(Bd + (int64_t)c * P.ldb + r); });
     __syncthreads();
     const int64_t lds = mr;
@@ -484,6 +486,7 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
             for (int i = 0; i < 4; ++i) pp[((lane >> 4) + 4 * i) * kLd + (lane & 15)] = acc[i];
         }
         __syncthreads();
+        TRSYL_STAMP(stamp, 4 + 2 * d);
         // phase B: each wave fills, solves (with power-of-two retries) and stores its leaves
         for (int li = w; li < nleaf; li += kWaves) {
             const int J = jlo + li, I = nla - 1 - (d - J);
@@ -491,6 +494,9 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
             int e = leaf_exponent(L, I, J, nla, Tc);
             const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
             const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+            // the first try is scaled by the largest growth shift the previous front needed (a
+            // guess: the leaf's own growth is unknown until it is solved once)
+            int t = uniform(L.tguess);
             double v[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -502,24 +508,26 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
                     v[i] = ldexp(rhs[i], -e) - g;
                     if (!(fabs(v[i]) <= Tc)) ok = 0;
                 }
-                LL.R[nn * kLd + mm] = v[i];
+                LL.R[nn * kLd + mm] = ldexp(v[i], -t);
             }
             wave_sync_lds();
+            if (li == 0) TRSYL_STAMP(stamp, 40 + 2 * d);
             const LeafPatch PT = leaf_setup(LL, L.rs[I], L.cs[J], smin);
             if (!PT.ok) ok = 0;
-            int t = 0;
-            bool done = false, blind = false;
+            bool done = false, blind = t > 0;
             for (int attempt = 0; attempt < 8 && uniform(__all(ok)); ++attempt) {
                 double vm;
                 if (!leaf_solve(LL, PT, L.rs[I], L.cs[J], nr, ncl, Tc, &vm)) ok = 0;
                 vm = wave_max(vm);
                 if (vm <= Tc) {
-                    // after a blind shift (the previous try overflowed), move the largest value
-                    // back up to about Tc / 4 so the leaf is not scaled further than needed
+                    // after a blind shift (a guessed one, or the previous try overflowed), move
+                    // the largest value back up to about Tc / 4 so the leaf is not scaled further
+                    // than needed (never below the shift the bound chose)
                     const int gap = vm > 0.0 ? ilogb(Tc) - ilogb(vm) - 2 : 0;
-                    if (!(blind && gap > 8)) { done = true; break; }
+                    const int tn = t - gap > 0 ? t - gap : 0;
+                    if (!(blind && gap > 8 && tn != t)) { done = true; break; }
                     blind = false;
-                    t -= gap;
+                    t = tn;
                 } else {
                     // linear in the right-hand side: shift it so the largest value lands below
                     // Tc / 2; an overflowed try gives no magnitude, so shift blindly
@@ -535,6 +543,8 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
             }
             if (!done) ok = 0;
             e += t;
+            if (lane == 0 && t > 0) atomicMax(&L.tnext, t);
+            if (li == 0) TRSYL_STAMP(stamp, 41 + 2 * d);
             // the leaf's infinity norm
             double rs = 0.0;
             if (lane < nr)
@@ -553,7 +563,12 @@ __device__ int tile_solve_scaled(const Plan &P, const double *Ad, const double *
         if (!ok) L.fail = 1;
         __threadfence_block();
         __syncthreads();
+        TRSYL_STAMP(stamp, 5 + 2 * d);
         if (uniform(L.fail)) break;
+        if (threadIdx.x == 0) {      // read after the next front's first barrier
+            L.tguess = L.tnext;
+            L.tnext = 0;
+        }
     }
     __syncthreads();
     if (uniform(L.fail)) return -1;
@@ -809,15 +824,20 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         const DevView vY = dev_view(Y, P.ldc, mr, nc);
         int done = 0;
         // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
-        // (the magnitude test is made wave-uniform: both branches below enclose barriers)
+        // (the magnitude test is made wave-uniform: both branches below enclose barriers).  A tile
+        // whose updates already had to scale it (e_in > 0) goes straight to the leaf-tiled robust
+        // solve: growth upstream predicts growth inside the tile, where the speculative attempt
+        // would run several fronts before its certificate fails.  e_in is fixed by the update
+        // order, so the choice (and the result) does not depend on timing.
         const int spec = uniform(!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016 ? 1 : 0);
-        if (spec)
+        const int try_fast = uniform(spec && e_in == 0 ? 1 : 0);
+        if (try_fast)
             done = uniform(tile_solve_fast(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));
         TRSYL_STAMP(stamp, 2);
         if (!done && spec) {
             // the leaf-tiled robust solve (the fast path left Y untouched)
             if (threadIdx.x == 0) atomicAdd(&P.stats[2], 1u);
-            const int es = uniform(tile_solve_scaled(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L));
+            const int es = uniform(tile_solve_scaled(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));
             if (es >= 0) {
                 e_syl = es;
                 done = 1;

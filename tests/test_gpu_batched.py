@@ -100,11 +100,19 @@ def test_batched_isolates_bad_problem(T):
         assert T.residual(A, B, Y, e, C) <= 1e-13
 
 
-def test_autotuner_table(T):
-    table = T.autotune_tiles(buckets=(64, 256), batch_flops=2e9, reps=1)
+def test_autotuner_table(T, tmp_path):
+    """The tuner ranks the candidates by the median of its timed runs on a batch that mixes
+    separated and growth problems, and writes the table (with the medians) as JSON."""
+    import json
+    path = str(tmp_path / "tiles.json")
+    table = T.autotune_tiles(buckets=(64, 256), batch_flops=2e9, reps=3, path=path)
     assert set(table) >= {64, 256}
     for b, t in table.items():
         assert t in T.TILE_CANDIDATES
+    rec = json.load(open(path))
+    assert {int(k): v for k, v in rec["tiles"].items()} == table
+    for b, med in rec["meta"]["median_ms"].items():
+        assert min(med, key=med.get) == str(table[int(b)])
     probs, _ = _mixed(1)
     out = T.solve_batched([p[0] for p in probs], [p[1] for p in probs], [p[2] for p in probs], "auto")
     for (A, B, C), (Y, e, info) in zip(probs, out):
