@@ -124,12 +124,16 @@ Layout make_layout(int64_t m, int64_t n, const Resolved &r)
 // update_index()).  The simulation's durations matter because the kernel follows the order
 // blindly: a solve is weighted solve_cost() update units.
 // ------------------------------------------------------------------------------------------
-// Tile solve time over tile update time.  Measured on MI355X at tile 128: 0.62 ms per solve
-// against 59 us per update (ratio 10.5).  The solve's length grows with tm + tn (leaf fronts),
-// the update's with tm tn k, so the ratio is scaled by (128 / tm) (128 / tn) for other tiles.
+// Tile solve time over tile update time.  Measured on MI355X at tile 128: 0.44 ms per solve
+// against 48 us per update (ratio 9; weights 7.5 / 9 / 10.5 / 12 gave 74.9 / 72.3 / 73.0 /
+// 75.8 ms per solve at m = n = 8192).  The solve's length grows with tm + tn (leaf fronts), the
+// update's with tm tn k, so the ratio is scaled by (128 / tm) (128 / tn) for other tiles.
+#ifndef TRSYL_SOLVE_COST
+#define TRSYL_SOLVE_COST 9.0
+#endif
 double solve_cost(int tm, int tn)
 {
-    const double c = 10.5 * (128.0 / tm) * (128.0 / tn);
+    const double c = TRSYL_SOLVE_COST * (128.0 / tm) * (128.0 / tn);
     return c < 1.0 ? 1.0 : (c > 256.0 ? 256.0 : c);
 }
 struct TaskCache {
