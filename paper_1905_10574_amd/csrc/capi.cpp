@@ -544,7 +544,7 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
         ++pos[p];
         push(p);
     }
-    if (k != B.ntasks) { hipHostFree(mt->pinned); delete mt; return nullptr; }
+    if (k != B.ntasks) { (void)hipHostFree(mt->pinned); delete mt; return nullptr; }
     cache[key] = mt;
     return mt;
 }

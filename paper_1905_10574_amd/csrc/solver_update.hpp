@@ -408,6 +408,35 @@ __device__ __forceinline__ d4 neg_scale4(d4 x, int sh)
     for (int i = 0; i < 4; ++i) y[i] = -(sh ? ldexp(x[i], sh) : x[i]);
     return y;
 }
+// The target block's values as load_target_acc leaves them, but loaded from clamped in-range
+// addresses without the masking select, so that the loads of all blocks are in flight together
+// (a select right after each block's loads makes the compiler wait for them, one round trip per
+// block); the masking happens in neg_scale4_masked, after every load has been issued.
+__device__ __forceinline__ void load_target_raw(d4 &acc, const DevView &Ct, int64_t ldc, int m0, int Mp, int n0,
+                                                int Np, int brow, int bcol)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int mm = m0 + 16 * brow + r;
+    const bool mok = mm < m0 + Mp;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int nn = n0 + 16 * bcol + q + 4 * i;
+        const bool ok = mok && nn < n0 + Np;
+        acc[i] = ld_dev(Ct, (int64_t)(ok ? nn : n0) * ldc + (ok ? mm : m0));
+    }
+}
+__device__ __forceinline__ d4 neg_scale4_masked(d4 x, int sh, int m0, int Mp, int n0, int Np, int brow, int bcol)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const bool mok = m0 + 16 * brow + r < m0 + Mp;
+    d4 y;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool ok = mok && n0 + 16 * bcol + q + 4 * i < n0 + Np;
+        y[i] = ok ? -(sh ? ldexp(x[i], sh) : x[i]) : 0.0;
+    }
+    return y;
+}
 // Stores D = -acc on the valid entries of the block (device scope) and adds the block's absolute
 // row sums to rs[row - rbase].
 __device__ __forceinline__ void store_neg_acc(const d4 &acc, const DevView &Ct, int64_t ldc, int m0, int Mp, int n0,
@@ -506,7 +535,10 @@ __device__ __forceinline__ void dma_stage(UpdateLds &L, int buf, const double *A
 // the scale decision of Algorithm 3 and returns (shC, shY); it is called once, after the first
 // pass's first two stages have been issued, so its loads overlap theirs.  The solved tile's
 // stage is multiplied by 2^shY in LDS when shY != 0.
-template <bool COL, class Decide>
+// SIMPLE: one pass of 8 x 8 blocks (113..128 rows and columns) and an even K, the common case,
+// for which the extra block row/column, the odd-K fix and the pass loop compile away (fewer live
+// registers, so the set-up does not spill).
+template <bool COL, bool SIMPLE, class Decide>
 __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *Aop, int64_t lda, const double *Bop,
                                                   int64_t ldb, int K, double *Ct, int rows, int cols, int rb_lo,
                                                   int nrb, UpdateLds &L, uint64_t *ustamp, Decide decide)
@@ -515,10 +547,10 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
     const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
     const int wr = w >> 2, wc = w & 3;
-    const int ncbt = (cols + 15) >> 4;
-    const int ngr = block_groups(nrb), ngc = block_groups(ncbt);
+    const int ncbt = SIMPLE ? 8 : (cols + 15) >> 4;
+    const int ngr = SIMPLE ? 1 : block_groups(nrb), ngc = SIMPLE ? 1 : block_groups(ncbt);
     const int nkc = (K + kUK - 1) / kUK;
-    const bool oddK = (K & 1) != 0;
+    const bool oddK = SIMPLE ? false : (K & 1) != 0;
     const DevView vB = dev_view(Bop, ldb, K, cols);
     const DevView vC = dev_view(Ct, P.ldc, rows, cols);
     const int nB = w < 5 ? 3 : 2;
@@ -526,7 +558,7 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
     bool decided = false;
     for (int gr = 0; gr < ngr; ++gr) {
         for (int gc = 0; gc < ngc; ++gc) {
-            const int R = group_size(nrb, gr, ngr), Cc = group_size(ncbt, gc, ngc);
+            const int R = SIMPLE ? 8 : group_size(nrb, gr, ngr), Cc = SIMPLE ? 8 : group_size(ncbt, gc, ngc);
             const int m0 = 16 * (rb_lo + 8 * gr), n0 = 16 * 8 * gc;
             const int Mp = (m0 + 16 * R < rows ? m0 + 16 * R : rows) - m0;
             const int Np = (n0 + 16 * Cc < cols ? n0 + 16 * Cc : cols) - n0;
@@ -544,7 +576,7 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
                 xc[j] = e < xrow ? e : 8;
                 if (e < nx) nxw = j + 1;
             }
-            const bool tailA = uniform(Mp > 128 ? 1 : 0) != 0;
+            const bool tailA = SIMPLE ? false : uniform(Mp > 128 ? 1 : 0) != 0;
             const bool full = nrm == 4 && ncm == 2;              // all eight main blocks live
             const int Lw = 2 + (tailA ? 2 : 0) + nB;             // loads per stage of this wave
             // every wave has left the previous pass's buffers
@@ -564,12 +596,12 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     acc[a][b] = zero4();
-                    if (a < nrm && b < ncm) load_target_acc(acc[a][b], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
+                    if (a < nrm && b < ncm) load_target_raw(acc[a][b], vC, P.ldc, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
                 }
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
                 accx[x] = zero4();
-                if (x < nxw) load_target_acc(accx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
+                if (x < nxw) load_target_raw(accx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
             }
             dma_stage<PA, PB>(L, 0, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np, 0, K);
             if (nkc > 1) dma_stage<PA, PB>(L, 1, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np, kUK, K);
@@ -582,9 +614,10 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int a = 0; a < 4; ++a) acc[a][b] = neg_scale4(acc[a][b], shC);
+                for (int a = 0; a < 4; ++a)
+                    acc[a][b] = neg_scale4_masked(acc[a][b], shC, m0, Mp, n0, Np, 4 * wr + a, 2 * wc + b);
 #pragma unroll
-            for (int x = 0; x < 3; ++x) accx[x] = neg_scale4(accx[x], shC);
+            for (int x = 0; x < 3; ++x) accx[x] = neg_scale4_masked(accx[x], shC, m0, Mp, n0, Np, xr[x], xc[x]);
             if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[2] = wall_clock64();
             for (int c = 0; c < nkc; ++c) {
                 const int buf = c % kDStages;
@@ -721,10 +754,14 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
         // FP64: the decision runs inside, overlapped with the first operand stages
         int shY = 0;
         auto dec = [&]() -> int2 { const int2 d = decide(); shC = d.x; shY = d.y; return d; };
-        if (colu)
-            update_passes_f64<true>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
-        else
-            update_passes_f64<false>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+        const bool simple = uniform(nrb == 8 && ((cols + 15) >> 4) == 8 && !(K & 1) ? 1 : 0) != 0;
+        if (colu) {
+            if (simple) update_passes_f64<true, true>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+            else update_passes_f64<true, false>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+        } else {
+            if (simple) update_passes_f64<false, true>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+            else update_passes_f64<false, false>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+        }
     } else {
         const int2 d = decide();
         shC = uniform(d.x);
