@@ -144,9 +144,11 @@ def critical_path(T, L, opts, m, n, Ac, Bc, C0, dev):
     if rc != 0:
         return None
     rec = trace.cpu().numpy().astype(np.uint64).reshape(ntasks, 4)
+    rec = rec[rec[:, 2] != 0]            # the tasks that ran (multi-term updates shorten the list)
     kind = (rec[:, 0] & 3).astype(int)
     tile = ((rec[:, 0] >> 8) & 0xFFFFF).astype(int)
     src = ((rec[:, 0] >> 28) & 0xFFFFF).astype(int)
+    first_u = ((rec[:, 0] >> 48) & 0xFFFF).astype(int)
     t0, t1 = rec[:, 1].astype(np.int64), rec[:, 2].astype(np.int64)     # 100 MHz wall clock
     sol = np.where(kind == 0)[0]
     s_start = np.zeros(pt * qt, np.int64); s_end = np.zeros(pt * qt, np.int64)
@@ -156,10 +158,23 @@ def critical_path(T, L, opts, m, n, Ac, Bc, C0, dev):
         T_ = tile[i]
         if T_ not in last_upd or t1[i] > t1[last_upd[T_]]:
             last_upd[T_] = i
+
+    def pred(i):
+        # the solved tile the update task i waited for last (a multi-term task has g sources:
+        # the solved tiles (k, l), k > i, and (i, j), j < l, ordered by anti-diagonal front, the
+        # column source first on a tie; it covers positions u .. u + g - 1 of that order)
+        if kind[i] != 3:
+            return int(src[i])
+        ti, tl = divmod(int(tile[i]), qt)
+        order = sorted([((pt - 1 - k) + tl, 0, k * qt + tl) for k in range(ti + 1, pt)] +
+                       [((pt - 1 - ti) + j, 1, ti * qt + j) for j in range(tl)])
+        cand = [o[2] for o in order[first_u[i]:first_u[i] + src[i]]]
+        return max(cand, key=lambda x: s_end[x])
+
     T_ = int(tile[sol[np.argmax(t1[sol])]])
     chain = [T_]
     while T_ in last_upd:
-        T_ = int(src[last_upd[T_]])
+        T_ = pred(last_upd[T_])
         chain.append(T_)
     chain.reverse()
     tk2 = float(np.mean((t1[sol] - t0[sol]) / 100.0))
@@ -175,7 +190,55 @@ def critical_path(T, L, opts, m, n, Ac, Bc, C0, dev):
             # workgroup time summed over tasks, by kind (the run's time split)
             "solve_tasks_wg_ms": round(float((t1[sol] - t0[sol]).sum()) / 1e5, 3),
             "update_tasks_wg_ms": round(float((t1[upd] - t0[upd]).sum()) / 1e5, 3),
-            "tile_update_us": round(float(np.mean((t1[upd] - t0[upd]) / 100.0)), 2) if upd.any() else None}
+            "update_task_us": round(float(np.mean((t1[upd] - t0[upd]) / 100.0)), 2) if upd.any() else None,
+            "update_tasks": int(upd.sum()),
+            "multi_term_tasks": int((kind == 3).sum())}
+
+
+def grouping_record(T, L, dev, m, Ac, Bc, C0, reps: int = 3):
+    """The tile-update grouping options on one workload (outside the timed region): per option,
+    one warm-up then the median of `reps` stream-synchronised solves (host clock), the scaling
+    events, the update tasks run and eq. (9).  Options: one task per update (the default), the
+    two same-front updates of a tile as one two-term update, all pending updates of a tile as one
+    multi-term update (deferred, left-looking)."""
+    import statistics
+    import torch
+    import trsyl_workloads as W
+    out = {}
+    for name, flags in (("single", 0), ("paired", T.FLAG_PAIRED_UPDATES), ("deferred", T.FLAG_DEFERRED_UPDATES)):
+        opts = T.make_opts(flags=flags)
+        ws = T.workspace_size(m, m, opts)
+        keep, ptr = T._aligned_workspace(ws, dev)
+        cnt = torch.zeros(4, dtype=torch.int32, device=dev)
+        e_t = torch.zeros(1, dtype=torch.int64, device=dev)
+        info_t = torch.zeros(1, dtype=torch.int32, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        times, Yc = [], None
+        for rep in range(1 + reps):
+            Yc = C0.clone()
+            cnt.zero_()
+            opts.counters = cnt.data_ptr()
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            rc = L.trsyl_robust(m, m, Ac.data_ptr(), m, Bc.data_ptr(), m, Yc.data_ptr(), m, e_t.data_ptr(),
+                                None, info_t.data_ptr(), ctypes.byref(opts), ptr, ws, stream)
+            if rc != 0:
+                raise RuntimeError(f"trsyl_robust returned {rc}")
+            torch.cuda.synchronize(dev)
+            if rep > 0:
+                times.append(time.perf_counter() - t0)
+        opts.counters = None
+        t = statistics.median(times)
+        pt = (m + opts.tile_m - 1) // opts.tile_m
+        # tasks in the list (the grouping does not depend on the number of workgroups)
+        ntasks = int(L.trsyl_debug_task_order(pt, pt, opts.tile_m, opts.tile_m, 1, 256, flags, None, 0))
+        out[name] = {"flags": flags, "ms_median": round(1e3 * t, 3), "gflops": round(W.flop_count(m, m) / t / 1e9, 2),
+                     "scale_log2": int(e_t.item()), "info": int(info_t.item()),
+                     "scaled_tile_updates": int(cnt[1].item()), "tasks": ntasks,
+                     "residual_eq9": residual_lib(T, Ac, Bc, Yc, e_t, C0, m, m)}
+        print(f"[bench] grouping {name} m={m}: {1e3 * t:.2f} ms", file=sys.stderr, flush=True)
+        del keep
+    return out
 
 
 def growth_record(T, L, dev, seed: int, reps: int = 3):
@@ -222,6 +285,7 @@ def growth_record(T, L, dev, seed: int, reps: int = 3):
     split = critical_path(T, L, opts, m, m, Ac, Bc, C0, dev)
     pt = (m + opts.tile_m - 1) // opts.tile_m
     print(f"[bench] growth: {1e3 * t:.2f} ms, e={int(e_t.item())}, events {c[:3]}", file=sys.stderr, flush=True)
+    grouping = grouping_record(T, L, dev, m, Ac, Bc, C0, reps)
     return {"workload": "growth m=n=4096: lambda_A U[-1,1]*1e-2, |lambda_A+lambda_B| in [1e-3,1e-2], "
                         "strict upper U[-10,10], C U[-1,1], seed %d" % seed,
             "tile": opts.tile_m, "ms_median": round(1e3 * t, 3), "reps": reps,
@@ -229,7 +293,7 @@ def growth_record(T, L, dev, seed: int, reps: int = 3):
             "info": int(info_t.item()), "residual_eq9": resid,
             "events": {"tile_solves": pt * pt, "leaf_tiled_tile_solves": c[2], "fallback_tile_solves": c[0],
                        "tile_updates": pt * pt * (pt - 1), "scaled_tile_updates": c[1]},
-            "time_split": split}
+            "time_split": split, "update_grouping": grouping}
 
 
 def paper_sweeps(args):
@@ -430,6 +494,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the eq. (9) residual check")
     ap.add_argument("--no-growth", action="store_true", help="skip the growth-workload record")
+    ap.add_argument("--no-grouping", action="store_true",
+                    help="skip the tile-update grouping records (paired and deferred multi-term updates)")
     ap.add_argument("--paper", action="store_true",
                     help="run the paper's experiment workloads instead (Sec. 3 test matrices, Sec. 4 experiments): mu = m, "
                          "nu = n at the --paper-sizes, then the cost-of-robustness sweep nu = 1e-2, "
@@ -557,6 +623,9 @@ def main():
     cpath = critical_path(T, L, opts, m, n, Ac, Bc, C0, dev) if args.scheduler == "dag" else None
     if cpath:
         print(f"[bench] critical path: {cpath}", file=sys.stderr, flush=True)
+    grouping = None
+    if not args.no_grouping and m == n and args.scheduler == "dag" and not args.tile and not args.slabs:
+        grouping = grouping_record(T, L, dev, m, Ac, Bc, C0)
     refine = None
     if not args.no_refine:
         cnt = torch.zeros(4, dtype=torch.int32, device=dev)
@@ -622,6 +691,7 @@ def main():
                      "kernel_ms": round(k_ms, 4)},
         "cpu_baseline": cpu,
         "critical_path": cpath,
+        "update_grouping": grouping,
         "fp32_refine": refine,
         "growth": growth,
         "residual_eq9": resid,

@@ -67,6 +67,10 @@ enum trsyl_scheduler {
     TRSYL_SCHED_FRONTS = 1, /* one launch per anti-diagonal front (stream ordered) */
 };
 
+#define TRSYL_FLAG_ROBUST_SOLVE 1
+#define TRSYL_FLAG_PAIRED_UPDATES 4
+#define TRSYL_FLAG_DEFERRED_UPDATES 8
+
 typedef struct trsyl_opts {
     int32_t tile_m;      /* tile size for A (rows of Y); 0 = default 128.  Range [16, 256] */
     int32_t tile_n;      /* tile size for B (columns of Y); 0 = tile_m */
@@ -79,13 +83,29 @@ typedef struct trsyl_opts {
                             remaining sweeps do nothing (no host synchronisation).
                             0 = default 1e-13 */
     int32_t workers;     /* persistent workgroups; 0 = one per compute unit */
-    int32_t flags;       /* bit 0: force the robust (non-speculative) tile solve */
+    int32_t flags;       /* bit 0: force the robust (non-speculative) tile solve.
+                            Grouping of the tile updates (Algorithm 3) into tasks, by default one
+                            task per update; with slabs = 1 and
+                            bit 2 (TRSYL_FLAG_PAIRED_UPDATES): the two updates of a tile whose
+                            solved tiles lie on the same anti-diagonal front (which become ready
+                            together) run as one two-term update -- one scale decision over both
+                            terms (ProtectUpdate with the sum of the terms' bounds), one read and
+                            write of the target; both schedulers group the same way, so their
+                            results stay bitwise equal;
+                            bit 3 (TRSYL_FLAG_DEFERRED_UPDATES): each tile takes all its pending
+                            updates as one multi-term update (left-looking; at most 128 terms per
+                            task), which reads and writes every target tile once -- in the
+                            persistent scheduler; the per-front scheduler then pairs as bit 2. */
     void *profile_events; /* optional host pointer to two caller-owned hipEvent_t: the library
                              records [0] right before and [1] right after the tile-DAG kernel(s)
                              on `stream`, so their elapsed time is the scheduler's duration */
-    uint64_t *trace;      /* optional device buffer of 4 * (number of tasks) uint64: for task t
-                             of the persistent scheduler, [4t] = task word, [4t+1] = start and
-                             [4t+2] = end (100 MHz wall clock), [4t+3] = workgroup */
+    uint64_t *trace;      /* optional device buffer of 4 * N uint64, N = pt qt + (updates) slabs
+                             the length of the task list with one task per update (pt = ceil(m /
+                             tile_m), qt = ceil(n / tile_n), updates = qt pt (pt-1)/2 +
+                             pt qt (qt-1)/2): for task t of the persistent scheduler, [4t] = task
+                             word, [4t+1] = start and [4t+2] = end (100 MHz wall clock), [4t+3] =
+                             workgroup; records past the last task (grouped updates make the list
+                             shorter) are left as they were */
     uint32_t *counters;   /* optional device buffer of 4 uint32, written on `stream` after the
                              solve: [0] tile solves that ran Algorithm 2 element by element
                              (both faster paths failed), [1] tile updates whose scale decision
@@ -288,6 +308,18 @@ int trsyl_residual(int64_t m, int64_t n, const double *A, int64_t lda, const dou
  */
 int trsyl_debug_protect_update(int32_t count, const double *in, int32_t *out, trsyl_stream_t stream);
 int trsyl_debug_protect_division(int32_t count, const double *in, int32_t *out, trsyl_stream_t stream);
+
+/*
+ * Diagnostics, host only (no device call): the static task order the persistent scheduler
+ * follows for a grid of pt x qt tiles (tile sizes tile_m x tile_n, `slabs` row slabs per update,
+ * `workers` workgroups, option flags as in trsyl_opts), written to out[0 .. cap) as task words:
+ * bits 0..1 kind (0 solve, 1 column update, 2 row update, 3 multi-term update), 2..7 slab,
+ * 8..27 target tile i * qt + l, 28..47 source tile (multi-term: number of terms g), 48..63 the
+ * update's position in the target's order (multi-term: the first of its g positions).  Returns
+ * the number of tasks (which may exceed cap; only cap are written), or a negative argument index.
+ */
+int64_t trsyl_debug_task_order(int32_t pt, int32_t qt, int32_t tile_m, int32_t tile_n, int32_t slabs,
+                               int32_t workers, int32_t flags, uint64_t *out, int64_t cap);
 
 /* Library version string. */
 const char *trsyl_version(void);

@@ -14,7 +14,7 @@ import torch
 
 __all__ = ["Opts", "lib", "solve", "solve_async", "adjoint", "adjoint_async", "grad", "residual", "trsyl",
            "solve_batched", "solve_batched_async", "autotune_tiles", "save_tile_table", "load_tile_table",
-           "debug_protect_update", "debug_protect_division", "TrsylFunction", "workspace_size",
+           "debug_protect_update", "debug_protect_division", "debug_task_order", "TrsylFunction", "workspace_size",
            "FP64", "FP32_REFINE", "SCHED_DAG", "SCHED_FRONTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         L.trsyl_debug_protect_update.restype = ctypes.c_int
         L.trsyl_debug_protect_division.argtypes = [ctypes.c_int32, _P, _P, _P]
         L.trsyl_debug_protect_division.restype = ctypes.c_int
+        L.trsyl_debug_task_order.argtypes = [ctypes.c_int32] * 7 + [_P, _I64]
+        L.trsyl_debug_task_order.restype = _I64
         _lib = L
     return _lib
 
@@ -251,6 +253,25 @@ def debug_protect_division(args) -> list[int]:
     if rc:
         raise RuntimeError(rc)
     return out.cpu().tolist()
+
+
+FLAG_ROBUST_SOLVE, FLAG_PAIRED_UPDATES, FLAG_DEFERRED_UPDATES = 1, 4, 8
+
+
+def debug_task_order(pt: int, qt: int, tile_m: int = 128, tile_n: int = 0, slabs: int = 1,
+                     workers: int = 256, flags: int = 0):
+    """The persistent scheduler's static task order for a pt x qt tile grid (host only), as a
+    numpy uint64 array of task words (see trsyl_debug_task_order)."""
+    import numpy as np
+    args = (int(pt), int(qt), int(tile_m), int(tile_n or tile_m), int(slabs), int(workers), int(flags))
+    n = lib().trsyl_debug_task_order(*args, None, 0)
+    if n < 0:
+        raise ValueError(f"trsyl_debug_task_order: {n}")
+    out = np.zeros(max(int(n), 1), dtype=np.uint64)
+    n2 = lib().trsyl_debug_task_order(*args, out.ctypes.data, int(n))
+    if n2 != n:
+        raise RuntimeError(f"trsyl_debug_task_order: {n2}")
+    return out[:n]
 
 
 def adjoint_async(A, B, W, opts: Opts | None = None):

@@ -141,8 +141,23 @@ struct TaskCache {
     uint64_t *pinned = nullptr;
 };
 
-std::vector<uint64_t> build_tasks(int pt, int qt, int slabs, int workers, double solve_cost)
+int tile_updates_of(int pt, int qt, int T) { return (pt - 1 - T / qt) + T % qt; }
+
+// How the updates of a tile are grouped into tasks: one task per update (and slab), the default;
+// the two updates whose sources lie on the same anti-diagonal front as one two-term task (they
+// become ready together); or all pending updates of a tile as one multi-term task (left-looking,
+// at most kMaxGroup terms per task).  Multi-term tasks need whole-tile update tasks (one slab).
+enum UpdatePolicy : int { kPolicySingle = 0, kPolicyFrontPairs = 1, kPolicyDeferred = 2 };
+int update_policy(int slabs, int flags)
 {
+    if (slabs > 1) return kPolicySingle;
+    if (flags & kFlagDeferredUpdates) return kPolicyDeferred;
+    return (flags & kFlagPairedUpdates) ? kPolicyFrontPairs : kPolicySingle;
+}
+
+std::vector<uint64_t> build_tasks(int pt, int qt, int slabs, int workers, double solve_cost, int policy)
+{
+    if (slabs > 1) policy = kPolicySingle;
     const int nt = pt * qt;
     std::vector<std::vector<int>> src(nt);
     std::vector<int> U(nt);
@@ -163,11 +178,25 @@ std::vector<uint64_t> build_tasks(int pt, int qt, int slabs, int workers, double
     int64_t seq = 0;
     auto front = [&](int T) { return (pt - 1 - T / qt) + T % qt; };
     auto push_solve = [&](int T) { ready.emplace(front(T), 0, seq++, make_task(kTaskSolve, 0, T, 0, 0)); };
+    // number of updates the next task of T covers
+    auto group_size = [&](int T) {
+        const int u = next_u[T], left = U[T] - u;
+        if (policy == kPolicyDeferred) return left < kMaxGroup ? left : kMaxGroup;
+        if (policy == kPolicyFrontPairs && left >= 2 && front(src[T][u]) == front(src[T][u + 1])) return 2;
+        return 1;
+    };
     auto try_start = [&](int T) {
         if (busy[T] || next_u[T] >= U[T]) return;
-        const int S = src[T][next_u[T]];
-        if (!solved[S]) return;
+        const int g = group_size(T);
+        for (int j = 0; j < g; ++j)
+            if (!solved[src[T][next_u[T] + j]]) return;
         busy[T] = 1;
+        if (g > 1) {
+            slabs_left[T] = 1;
+            ready.emplace(front(T), 1, seq++, make_task(kTaskGroupUpdate, 0, T, g, next_u[T]));
+            return;
+        }
+        const int S = src[T][next_u[T]];
         slabs_left[T] = slabs;
         const int kind = (S % qt == T % qt) ? kTaskColUpdate : kTaskRowUpdate;
         for (int s = 0; s < slabs; ++s) ready.emplace(front(T), 1, seq++, make_task(kind, s, T, S, next_u[T]));
@@ -185,7 +214,11 @@ std::vector<uint64_t> build_tasks(int pt, int qt, int slabs, int workers, double
             ready.pop();
             order.push_back(task);
             --free_w;
-            events.emplace(now + (task_kind(task) == kTaskSolve ? ts : tu), seq++, task);
+            // a g-term update: one target read and write and g products (about half of a
+            // single update's time is the products)
+            const int kd = task_kind(task);
+            const double dt = kd == kTaskSolve ? ts : (kd == kTaskGroupUpdate ? 0.5 + 0.5 * task_S(task) : tu);
+            events.emplace(now + dt, seq++, task);
         }
         if (events.empty()) break;
         const Event ev = events.top();
@@ -201,33 +234,51 @@ std::vector<uint64_t> build_tasks(int pt, int qt, int slabs, int workers, double
             for (int j = l + 1; j < qt; ++j) try_start(k * qt + j);
         } else if (--slabs_left[T] == 0) {
             busy[T] = 0;
-            if (++next_u[T] == U[T]) push_solve(T);
+            next_u[T] += task_kind(task) == kTaskGroupUpdate ? task_S(task) : 1;
+            if (next_u[T] == U[T]) push_solve(T);
             else try_start(T);
         }
     }
     return order;
 }
 
-const TaskCache *get_tasks(int pt, int qt, int slabs, int workers, int tm, int tn)
+// The kernel trusts the list: every tile solved once, every update covered once (in slabs or in
+// a group), every index in range, at most count_tasks entries.
+bool tasks_valid(const std::vector<uint64_t> &tasks, int pt, int qt, int slabs)
+{
+    int64_t solves = 0, covered = 0;
+    bool ok = (int64_t)tasks.size() <= count_tasks(pt, qt, slabs);
+    for (const uint64_t t : tasks) {
+        const int kd = task_kind(t);
+        if (task_T(t) >= pt * qt || task_slab(t) >= slabs) ok = false;
+        if (kd == kTaskSolve) ++solves;
+        else if (kd == kTaskGroupUpdate) {
+            const int gsz = task_S(t);
+            if (gsz < 2 || gsz > kMaxGroup || slabs != 1 ||
+                task_u(t) + gsz > tile_updates_of(pt, qt, task_T(t)))
+                ok = false;
+            covered += (int64_t)gsz * slabs;
+        } else {
+            if (task_S(t) >= pt * qt) ok = false;
+            covered += 1;
+        }
+    }
+    return ok && solves == (int64_t)pt * qt && covered == count_tasks(pt, qt, slabs) - (int64_t)pt * qt;
+}
+
+const TaskCache *get_tasks(int pt, int qt, int slabs, int workers, int tm, int tn, int policy)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, int>, TaskCache *> cache;
+    static std::map<std::tuple<int, int, int, int, int, int, int>, TaskCache *> cache;
     std::lock_guard<std::mutex> g(mu);
-    const auto key = std::make_tuple(pt, qt, slabs, workers, tm, tn);
+    const auto key = std::make_tuple(pt, qt, slabs, workers, tm, tn, policy);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     TaskCache *tc = new TaskCache;
-    tc->tasks = build_tasks(pt, qt, slabs, workers, solve_cost(tm, tn));
-    // the kernel trusts the list: exactly count_tasks entries, every tile index in range
-    if ((int64_t)tc->tasks.size() != count_tasks(pt, qt, slabs)) {
+    tc->tasks = build_tasks(pt, qt, slabs, workers, solve_cost(tm, tn), policy);
+    if (!tasks_valid(tc->tasks, pt, qt, slabs)) {
         delete tc;
         return nullptr;
-    }
-    for (const uint64_t t : tc->tasks) {
-        if (task_T(t) >= pt * qt || task_S(t) >= pt * qt || task_slab(t) >= slabs) {
-            delete tc;
-            return nullptr;
-        }
     }
     const size_t bytes = tc->tasks.size() * sizeof(uint64_t);
     if (hipHostMalloc((void **)&tc->pinned, bytes ? bytes : 8, hipHostMallocDefault) != hipSuccess) {
@@ -299,8 +350,9 @@ int solve_core(int64_t m, int64_t n, const double *A, int64_t lda, const double 
     if (launch_fill_zero(ws + L.zero_begin, L.zero_end - L.zero_begin, stream) != hipSuccess) return -100;
     if (launch_setup(P, stream) != hipSuccess) return -100;
     if (r.scheduler == TRSYL_SCHED_DAG) {
-        const TaskCache *tc = get_tasks(L.pt, L.qt, r.slabs, L.workers, r.tm, r.tn);
+        const TaskCache *tc = get_tasks(L.pt, L.qt, r.slabs, L.workers, r.tm, r.tn, update_policy(r.slabs, r.flags));
         if (!tc) return -100;
+        P.ntasks = (int)tc->tasks.size();
         if (hipMemcpyAsync(ws + L.tasks, tc->pinned, tc->tasks.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return -100;
@@ -509,6 +561,7 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
     for (int p = 0; p < B.count; ++p) {
         key.push_back(B.L[p].pt); key.push_back(B.L[p].qt); key.push_back(B.r[p].slabs);
         key.push_back(B.r[p].tm); key.push_back(B.r[p].tn);
+        key.push_back(update_policy(B.r[p].slabs, B.r[p].flags));
         key.push_back(m[p] * n[p] * (m[p] + n[p]));
     }
     std::lock_guard<std::mutex> g(mu);
@@ -517,7 +570,8 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
     std::vector<const TaskCache *> lists(B.count, nullptr);
     for (int p = 0; p < B.count; ++p) {
         if (B.L[p].pt && B.L[p].qt) {
-            lists[p] = get_tasks(B.L[p].pt, B.L[p].qt, B.r[p].slabs, B.workers, B.r[p].tm, B.r[p].tn);
+            lists[p] = get_tasks(B.L[p].pt, B.L[p].qt, B.r[p].slabs, B.workers, B.r[p].tm, B.r[p].tn,
+                                 update_policy(B.r[p].slabs, B.r[p].flags));
             if (!lists[p]) return nullptr;
         }
     }
@@ -530,7 +584,8 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
     };
     for (int p = 0; p < B.count; ++p) if (lists[p]) push(p);
     MergedTasks *mt = new MergedTasks;
-    mt->n = B.ntasks;
+    mt->n = 0;
+    for (int p = 0; p < B.count; ++p) if (lists[p]) mt->n += (int64_t)lists[p]->tasks.size();
     const size_t bytes = 12 * (size_t)B.ntasks + 8;
     if (hipHostMalloc((void **)&mt->pinned, bytes, hipHostMallocDefault) != hipSuccess) { delete mt; return nullptr; }
     uint32_t *prob = (uint32_t *)(mt->pinned + B.ntasks);
@@ -544,7 +599,7 @@ const MergedTasks *get_merged(const BLayout &B, const int64_t *m, const int64_t 
         ++pos[p];
         push(p);
     }
-    if (k != B.ntasks) { (void)hipHostFree(mt->pinned); delete mt; return nullptr; }
+    if (k != mt->n || mt->n > B.ntasks) { (void)hipHostFree(mt->pinned); delete mt; return nullptr; }
     cache[key] = mt;
     return mt;
 }
@@ -612,7 +667,7 @@ int batched_core(const BLayout &BL, int32_t count, const int64_t *m, const int64
     bl.blocks_consistency = oK[count];
     bl.tasks = (const uint64_t *)(ws + BL.tasks);
     bl.tprob = (const uint32_t *)(ws + BL.tprob);
-    bl.ntasks = BL.ntasks;
+    bl.ntasks = mt->n;
     bl.ticket = (uint32_t *)(ws + BL.ticket);
     bl.scratch = (double *)(ws + BL.scratch);
     bl.workers = BL.workers;
@@ -827,6 +882,23 @@ int trsyl_debug_protect_division(int32_t count, const double *in, int32_t *out, 
     if (count < 0) return -1;
     if (count > 0 && (bad_ptr(in) || bad_ptr(out))) return -2;
     return launch_debug_protect(1, count, in, out, (hipStream_t)s) == hipSuccess ? 0 : -100;
+}
+
+int64_t trsyl_debug_task_order(int32_t pt, int32_t qt, int32_t tile_m, int32_t tile_n, int32_t slabs,
+                               int32_t workers, int32_t flags, uint64_t *out, int64_t cap)
+{
+    if (pt < 1 || pt > 4096) return -1;
+    if (qt < 1 || qt > 4096 || (int64_t)pt * qt >= (1 << 20)) return -2;
+    if (tile_m < 16 || tile_m > 256) return -3;
+    if (tile_n < 16 || tile_n > 256) return -4;
+    if (slabs < 1 || slabs > 32) return -5;
+    if (workers < 1) return -6;
+    if (cap < 0 || (cap > 0 && !out)) return -9;
+    const std::vector<uint64_t> t =
+        build_tasks(pt, qt, slabs, workers, solve_cost(tile_m, tile_n), update_policy(slabs, flags));
+    if (!tasks_valid(t, pt, qt, slabs)) return -100;
+    for (int64_t i = 0; i < (int64_t)t.size() && i < cap; ++i) out[i] = t[i];
+    return (int64_t)t.size();
 }
 
 

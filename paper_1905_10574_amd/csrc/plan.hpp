@@ -17,14 +17,21 @@ constexpr int kMaxColBlocksPerWave = 3;   // 17 column blocks over 8 waves
 // Plan flags
 constexpr int kFlagRobustSolve = 1;   // skip the speculative tile solve
 constexpr int kFlagF32Updates = 2;    // tile updates on FP32 MFMA (the precision form's solves)
+constexpr int kFlagPairedUpdates = 4; // the two updates of a tile whose sources share an
+                                      // anti-diagonal front as one two-term task
+constexpr int kFlagDeferredUpdates = 8;   // persistent scheduler: each tile takes all its updates
+                                          // in one multi-term task (left-looking), at most
+                                          // kMaxGroup terms per task
+constexpr int kMaxGroup = 128;        // terms of one multi-term update task
 
 // Task encoding for the persistent scheduler (one 64-bit word):
-//   bits  0..1   kind (0 = solve, 1 = column update, 2 = row update)
+//   bits  0..1   kind (0 = solve, 1 = column update, 2 = row update, 3 = multi-term update)
 //   bits  2..7   slab
 //   bits  8..27  target tile index T = i * qt + l
-//   bits 28..47  source tile index S
-//   bits 48..63  u: the update's position in the target's fixed update order
-enum TaskKind : int { kTaskSolve = 0, kTaskColUpdate = 1, kTaskRowUpdate = 2 };
+//   bits 28..47  source tile index S; for a multi-term update the number of terms g
+//   bits 48..63  u: the update's position in the target's fixed update order (multi-term: the
+//                first of the g consecutive updates u .. u + g - 1 it applies)
+enum TaskKind : int { kTaskSolve = 0, kTaskColUpdate = 1, kTaskRowUpdate = 2, kTaskGroupUpdate = 3 };
 
 __host__ __device__ inline uint64_t make_task(int kind, int slab, int T, int S, int u)
 {
@@ -120,6 +127,14 @@ __host__ __device__ inline int consistency_per_tile(int tm, int tn)
     return per < 8 ? per : 8;
 }
 
+// Tasks of a solve with one task per tile update and slab (the longest task list; the
+// optional phase stamps of the stamped build are stored after this many trace records).
+__host__ __device__ inline int64_t max_tasks(const Plan &P)
+{
+    const int64_t upd = (int64_t)P.qt * P.pt * (P.pt - 1) / 2 + (int64_t)P.pt * P.qt * (P.qt - 1) / 2;
+    return (int64_t)P.pt * P.qt + upd * P.slabs;
+}
+
 __host__ __device__ inline int tile_updates(const Plan &P, int T)
 {
     const int i = T / P.qt, l = T % P.qt;
@@ -144,6 +159,34 @@ __host__ __device__ inline int update_index(int pt, int i, int l, int ks, int ls
         if (cols_upto > pt - 1 - i) cols_upto = pt - 1 - i;
         return cols_upto + ls;
     }
+}
+
+// The source of update u of target (i, l) in the order of update_index(): the column sources
+// (k, l), k = pt-1 down to i+1, sit on fronts l .. l + pt-2-i, the row sources (i, j), j = 0 ..
+// l-1, on fronts pt-1-i .. pt-2-i+l; the order is by front, the column source first on a tie.
+// Returns the source tile's (row, column) block index in (ks, ls).
+__host__ __device__ inline void update_source(int pt, int i, int l, int u, int *ks, int *ls)
+{
+    const int nc = pt - 1 - i, fc = l;          // column sources: count, first front
+    const int nr = l, fr = pt - 1 - i;          // row sources
+    // sources on fronts before f: clamp(f - fc, 0, nc) + clamp(f - fr, 0, nr); the last front
+    // f with fewer than u + 1 sources before it holds source u
+    auto before = [&](int f) {
+        const int a = f - fc < 0 ? 0 : (f - fc > nc ? nc : f - fc);
+        const int b = f - fr < 0 ? 0 : (f - fr > nr ? nr : f - fr);
+        return a + b;
+    };
+    // before() does not decrease: the largest f < pt + l with before(f) <= u, by a search of a
+    // fixed number of steps (tile indices fit in 20 bits), so that lanes never diverge in a loop
+    int f = 0;
+#pragma unroll
+    for (int step = 1 << 20; step > 0; step >>= 1) {
+        const int mid = f + step;
+        if (mid < pt + l && before(mid) <= u) f = mid;
+    }
+    const bool col_here = f >= fc && f < fc + nc;
+    if (col_here && u == before(f)) { *ks = pt - 1 - (f - l); *ls = l; }
+    else { *ks = i; *ls = f - (pt - 1 - i); }
 }
 
 }  // namespace trsyl

@@ -161,6 +161,45 @@ __device__ __forceinline__ bool wait_count(const Plan &P, const uint32_t *ctr, u
     return true;
 }
 
+// Dependency waits of a task, spread over the threads: for a solve, thread 0 waits for every
+// update of the tile; for an update, thread 0 waits for the source's solve and the target's
+// previous version; for a multi-term update of g terms, thread t < g waits for the solve of term
+// t's source and thread 0 also for the target's version u0.  Returns false on a watchdog timeout
+// (the status is set).
+__device__ __forceinline__ bool task_wait(const Plan &P, uint64_t task, int kind, int T, uint32_t slabs)
+{
+    const uint64_t t0 = wall_clock64();
+    bool ok = true;
+    if (kind == kTaskGroupUpdate) {
+        const int g = task_S(task), u0 = task_u(task);
+        if ((int)threadIdx.x < g) {
+            int ks, ls;
+            update_source(P.pt, T / P.qt, T % P.qt, u0 + (int)threadIdx.x, &ks, &ls);
+            const int S = ks * P.qt + ls;
+            ok = wait_count(P, &P.ver[S], (uint32_t)(tile_updates(P, S) + 1) * slabs, t0);
+        }
+        if (threadIdx.x == 0) ok = ok && wait_count(P, &P.ver[T], (uint32_t)u0 * slabs, t0);
+    } else if (threadIdx.x == 0) {
+        if (kind == kTaskSolve) {
+            ok = wait_count(P, &P.ver[T], (uint32_t)tile_updates(P, T) * slabs, t0);
+        } else {
+            const int S = task_S(task), u = task_u(task);
+            ok = wait_count(P, &P.ver[S], (uint32_t)(tile_updates(P, S) + 1) * slabs, t0) &&
+                 wait_count(P, &P.ver[T], (uint32_t)u * slabs, t0);
+        }
+    }
+    // on a timeout the task is skipped, but its counter still moves so that every other
+    // workgroup drains as well; the status reports the failure
+    if (!ok) set_status(P.status, kWatchdog);
+    return ok;
+}
+
+// What a finished task adds to its target's counter (completed modifications x slabs).
+__device__ __forceinline__ uint32_t task_increment(uint64_t task, int kind, uint32_t slabs)
+{
+    return kind == kTaskSolve ? slabs : (kind == kTaskGroupUpdate ? (uint32_t)task_S(task) * slabs : 1u);
+}
+
 // The persistent loop has one latch and no divergent exits: every value that decides a branch
 // around a barrier is read back from LDS and made uniform, thread-0-only blocks are fenced by
 // barriers on both sides, and the back-edge follows a barrier.
@@ -175,38 +214,28 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
     const uint32_t slabs = (uint32_t)P.slabs;
     const uint32_t ntasks = (uint32_t)P.ntasks;
     for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(P.ticket, 1u);
+        if (threadIdx.x == 0) {
+            s_ticket = atomicAdd(P.ticket, 1u);
+            s_ok = 1;
+        }
         __syncthreads();
         const uint32_t t = uniform(s_ticket);
         if (t >= ntasks) break;
         const uint64_t task = P.tasks[t];
         const int kind = uniform(task_kind(task)), T = uniform(task_T(task));
-        if (threadIdx.x == 0) {
-            const uint64_t t0 = wall_clock64();
-            bool ok;
-            if (kind == kTaskSolve) {
-                ok = wait_count(P, &P.ver[T], (uint32_t)tile_updates(P, T) * slabs, t0);
-            } else {
-                const int S = task_S(task), u = task_u(task);
-                ok = wait_count(P, &P.ver[S], (uint32_t)(tile_updates(P, S) + 1) * slabs, t0) &&
-                     wait_count(P, &P.ver[T], (uint32_t)u * slabs, t0);
-            }
-            s_ok = ok ? 1 : 0;
-            // on a timeout the task is skipped, but its counter still moves so that every
-            // other workgroup drains as well; the status reports the failure
-            if (!ok) set_status(P.status, kWatchdog);
-        }
+        if (!task_wait(P, task, kind, T, slabs)) s_ok = 0;
         __syncthreads();
         const uint64_t tstart = wall_clock64();
         if (uniform(s_ok)) {
             if (kind == kTaskSolve) run_solve(P, T, scratch, L.sol);
             else {
 #ifdef TRSYL_PHASE_STAMPS
-                uint64_t *us = P.trace ? P.trace + 4 * (size_t)P.ntasks + 80 * (size_t)P.pt * P.qt + 8 * (size_t)t : nullptr;
+                uint64_t *us = P.trace ? P.trace + 4 * (size_t)max_tasks(P) + 80 * (size_t)P.pt * P.qt + 8 * (size_t)t : nullptr;
 #else
                 uint64_t *us = nullptr;
 #endif
-                run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd, us);
+                if (kind == kTaskGroupUpdate) run_update_group(P, T, task_u(task), task_S(task), L.upd, us);
+                else run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd, us);
             }
         }
         if (P.trace && threadIdx.x == 0) {
@@ -220,7 +249,7 @@ __global__ void __launch_bounds__(kThreads) k_dag(Plan Pk)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&P.ver[T], kind == kTaskSolve ? slabs : 1u, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&P.ver[T], task_increment(task, kind, slabs), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
@@ -269,6 +298,22 @@ __global__ void __launch_bounds__(kThreads) k_front_update(Plan Pk, int d, int k
     const int T = ti * P.qt + tl, S = ks * P.qt + ls;
     const int u = update_index(P.pt, ti, tl, ks, ls);
     run_update(P, kind, T, S, u, slab, L, nullptr);
+}
+
+// One workgroup per tile T: the updates of T whose sources lie on front d -- the column source
+// (k, l) and the row source (i, j) on that front -- as one two-term update when both exist (the
+// grouping of the persistent scheduler's task list), else as a single update.
+__global__ void __launch_bounds__(kThreads) k_front_group(Plan Pk, int d)
+{
+    const Plan P = uniform_plan(Pk);
+    __shared__ UpdateLds L;
+    if (plan_skipped(P) || uniform(*(volatile int32_t *)P.status) >= kBadStructure) return;
+    const int T = blockIdx.x, i = T / P.qt, l = T % P.qt;
+    const int ks = P.pt - 1 - (d - l), ls = d - (P.pt - 1 - i);
+    const bool col = d - l >= 0 && ks > i, row = ls >= 0 && ls < l;
+    if (col && row) run_update_group(P, T, update_index(P.pt, i, l, ks, l), 2, L, nullptr);
+    else if (col) run_update(P, kTaskColUpdate, T, ks * P.qt + l, update_index(P.pt, i, l, ks, l), 0, L, nullptr);
+    else if (row) run_update(P, kTaskRowUpdate, T, i * P.qt + ls, update_index(P.pt, i, l, i, ls), 0, L, nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -401,31 +446,20 @@ __global__ void __launch_bounds__(kThreads) k_dag_b(const Plan *plans, const uin
         const Plan P = uniform_plan(plans[p]);
         const uint32_t slabs = (uint32_t)P.slabs;
         const int kind = uniform(task_kind(task)), T = uniform(task_T(task));
-        if (threadIdx.x == 0) {
-            const bool bad = plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure;
-            bool ok = true;
-            if (!bad) {
-                const uint64_t t0 = wall_clock64();
-                if (kind == kTaskSolve) {
-                    ok = wait_count(P, &P.ver[T], (uint32_t)tile_updates(P, T) * slabs, t0);
-                } else {
-                    const int S = task_S(task), u = task_u(task);
-                    ok = wait_count(P, &P.ver[S], (uint32_t)(tile_updates(P, S) + 1) * slabs, t0) &&
-                         wait_count(P, &P.ver[T], (uint32_t)u * slabs, t0);
-                }
-                if (!ok) set_status(P.status, kWatchdog);
-            }
-            s_ok = (ok && !bad) ? 1 : 0;
-        }
+        if (threadIdx.x == 0)
+            s_ok = (plan_skipped(P) || *(volatile int32_t *)P.status >= kBadStructure) ? 0 : 1;
+        __syncthreads();
+        if (uniform(s_ok) && !task_wait(P, task, kind, T, slabs)) s_ok = 0;
         __syncthreads();
         if (uniform(s_ok)) {
             if (kind == kTaskSolve) run_solve(P, T, scratch, L.sol);
+            else if (kind == kTaskGroupUpdate) run_update_group(P, T, task_u(task), task_S(task), L.upd, nullptr);
             else run_update(P, kind, T, task_S(task), task_u(task), task_slab(task), L.upd, nullptr);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&P.ver[T], kind == kTaskSolve ? slabs : 1u, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&P.ver[T], task_increment(task, kind, slabs), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
@@ -491,6 +525,11 @@ hipError_t launch_fronts(const Plan &P, hipStream_t s)
         const int lmax = d < P.qt - 1 ? d : P.qt - 1;
         const int nsrc = lmax - lmin + 1;
         hipLaunchKernelGGL(k_front_solve, dim3(nsrc), dim3(kThreads), 0, s, P, d);
+        if (P.slabs == 1 && (P.flags & (kFlagPairedUpdates | kFlagDeferredUpdates))) {
+            if (d < nf - 1)
+                hipLaunchKernelGGL(k_front_group, dim3(P.pt * P.qt), dim3(kThreads), 0, s, P, d);
+            continue;
+        }
         if (P.pt > 1)
             hipLaunchKernelGGL(k_front_update, dim3(nsrc * (P.pt - 1) * P.slabs), dim3(kThreads), 0, s,
                                P, d, (int)kTaskColUpdate);

@@ -803,7 +803,7 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
     double nrm = 0.0;
     int pert = 0;
 #ifdef TRSYL_PHASE_STAMPS
-    uint64_t *stamp = P.trace ? P.trace + 4 * (size_t)P.ntasks + 80 * (size_t)T : nullptr;
+    uint64_t *stamp = P.trace ? P.trace + 4 * (size_t)max_tasks(P) + 80 * (size_t)T : nullptr;
 #else
     uint64_t *stamp = nullptr;
 #endif

@@ -37,6 +37,10 @@ struct UpdateLds {
     double stage[kDStages * kDStage];
     double rs[kWaves][kMaxTile + 3];  // per-wave partial absolute row sums of the slab
     double red[kWaves];
+    // multi-term update, per term: the solved tile, its first k (row of A_ik / column of B_lj),
+    // its K, 1 for a column update (0: row update) and the exponent shift of the solved tile
+    int gS[kMaxGroup], gk0[kMaxGroup], gK[kMaxGroup], gcol[kMaxGroup], gsh[kMaxGroup];
+    double gyn[kMaxGroup], gtn[kMaxGroup];   // ||Y_S||_inf of the solved tile, ||A_ik|| or ||B_lj||
 };
 static_assert(2 * 2 * kUK * kUS <= kDStages * kDStage, "FP32 stages fit the FP64 ring");
 template <class T> __device__ __forceinline__ T *stage_A(UpdateLds &L, int buf)
@@ -531,30 +535,105 @@ __device__ __forceinline__ void dma_stage(UpdateLds &L, int buf, const double *A
     }
 }
 
-// One update slab in FP64 (see update_passes for the block layout of the waves).  `decide` runs
-// the scale decision of Algorithm 3 and returns (shC, shY); it is called once, after the first
-// pass's first two stages have been issued, so its loads overlap theirs.  The solved tile's
-// stage is multiplied by 2^shY in LDS when shY != 0.
-// SIMPLE: one pass of 8 x 8 blocks (113..128 rows and columns) and an even K, the common case,
-// for which the extra block row/column, the odd-K fix and the pass loop compile away (fewer live
-// registers, so the set-up does not spill).
-template <bool COL, bool SIMPLE, class Decide>
-__device__ __forceinline__ void update_passes_f64(const Plan &P, const double *Aop, int64_t lda, const double *Bop,
-                                                  int64_t ldb, int K, double *Ct, int rows, int cols, int rb_lo,
-                                                  int nrb, UpdateLds &L, uint64_t *ustamp, Decide decide)
+// One term of an FP64 update pass: Aop (rows x K, column-major, ld lda) times Bop (K x cols,
+// column-major, ld ldb).  The solved tile -- the B operand of a column update, the A operand of a
+// row update -- is read at device scope (other workgroups write it) and enters the product times
+// 2^shY; the A / B panels keep the default cache policy, so that they stay in the XCD's L2 across
+// the many updates that read them.
+struct UpdTerm {
+    const double *Aop;
+    int64_t lda;
+    const double *Bop;
+    int64_t ldb;
+    int K, col, shY;
+};
+
+// Issue stage kc (k in [kc, kc + 16)) of term tm into ring buffer `buf`.  KIND: 1 every term is a
+// column update, 2 every term a row update (the policies are then fixed at compile time), 0 mixed.
+template <int KIND>
+__device__ __forceinline__ void term_stage(UpdateLds &L, int buf, const UpdTerm &tm, int m0, int Mp, bool tailA,
+                                           int n0, int Np, int kc)
 {
-    constexpr int PA = COL ? 0 : kPolicyDevice, PB = COL ? kPolicyDevice : 0;
+    if (KIND == 0 ? tm.col != 0 : KIND == 1)
+        dma_stage<0, kPolicyDevice>(L, buf, tm.Aop, tm.lda, m0, Mp, tailA, tm.Bop, tm.ldb, n0, Np, kc, tm.K);
+    else
+        dma_stage<kPolicyDevice, 0>(L, buf, tm.Aop, tm.lda, m0, Mp, tailA, tm.Bop, tm.ldb, n0, Np, kc, tm.K);
+}
+
+// k = K - 1 of B column n0 + threadIdx.x (threads below Np): the stage loads k in pairs, so an odd
+// K's last k is staged separately.
+__device__ __forceinline__ double term_fix(const UpdTerm &tm, int n0, int Np)
+{
+    if ((int)threadIdx.x >= Np) return 0.0;
+    const int64_t idx = (int64_t)(n0 + threadIdx.x) * tm.ldb + (tm.K - 1);
+    if (tm.col) return ld_dev(dev_view(tm.Bop, tm.ldb, tm.K, n0 + Np), idx);
+    return ldg(tm.Bop + idx);
+}
+
+// Cursors over the concatenated stages of g terms: term t, first k of the stage kc; terms with
+// K = 0 contribute no stage.  A term is fetched only when a cursor enters it, and each cursor
+// keeps only what its side of the loop needs (the issuing side the operands, the multiplying
+// side the term's K, kind and shift), to spare registers in the stage loop.
+struct IssueCursor {
+    int t, kc, K, col;
+    const double *Aop, *Bop;
+    int64_t lda, ldb;
+    __device__ __forceinline__ void set(const UpdTerm &x)
+    {
+        K = x.K; col = x.col; Aop = x.Aop; Bop = x.Bop; lda = x.lda; ldb = x.ldb;
+    }
+    __device__ __forceinline__ UpdTerm term() const { return UpdTerm{Aop, lda, Bop, ldb, K, col, 0}; }
+};
+struct ProcCursor {
+    int t, kc, K, col, shY;
+    __device__ __forceinline__ void set(const UpdTerm &x) { K = x.K; col = x.col; shY = x.shY; }
+};
+template <class C, class Term>
+__device__ __forceinline__ void cursor_start(C &c, int g, Term term)
+{
+    c.t = 0;
+    c.kc = 0;
+    c.set(term(0));
+    while (c.t < g && c.kc >= c.K) {
+        ++c.t;
+        if (c.t < g) c.set(term(c.t));
+    }
+}
+template <class C, class Term>
+__device__ __forceinline__ void cursor_next(C &c, int g, Term term)
+{
+    c.kc += kUK;
+    while (c.t < g && c.kc >= c.K) {
+        ++c.t;
+        c.kc = 0;
+        if (c.t < g) c.set(term(c.t));
+    }
+}
+
+// One update slab in FP64 over g terms (a single update: g = 1), the terms' K dimensions
+// concatenated into one stream of 16-k stages:
+//     D = 2^shC C - sum_t 2^shY_t Aop_t Bop_t.
+// `term(t)` returns term t (its shY valid once `decide` has run); `decide` runs the scale decision
+// and returns shC; it is called once, after the first pass's first two stages have been issued,
+// so that its loads overlap theirs, and leaves the shifts it stores visible to every wave (the
+// stage cursor fetches them right after it returns).  See update_passes for the block layout of the waves.
+// SIMPLE: one pass of 8 x 8 blocks (113..128 rows and columns), for which the extra block
+// row/column and the pass loop compile away (fewer live registers, so the set-up does not spill).
+template <bool SIMPLE, int KIND, class Term, class Decide>
+__device__ __forceinline__ void update_stream_f64(const Plan &P, int g, Term term, double *Ct, int rows, int cols,
+                                                  int rb_lo, int nrb, UpdateLds &L, uint64_t *ustamp, Decide decide)
+{
     const int w = uniform((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
     const int wr = w >> 2, wc = w & 3;
     const int ncbt = SIMPLE ? 8 : (cols + 15) >> 4;
     const int ngr = SIMPLE ? 1 : block_groups(nrb), ngc = SIMPLE ? 1 : block_groups(ncbt);
-    const int nkc = (K + kUK - 1) / kUK;
-    const bool oddK = SIMPLE ? false : (K & 1) != 0;
-    const DevView vB = dev_view(Bop, ldb, K, cols);
+    int nkc = 0;
+    for (int t = 0; t < g; ++t) nkc += (term(t).K + kUK - 1) / kUK;
+    nkc = uniform(nkc);
     const DevView vC = dev_view(Ct, P.ldc, rows, cols);
     const int nB = w < 5 ? 3 : 2;
-    int shC = 0, shY = 0;
+    int shC = 0;
     bool decided = false;
     for (int gr = 0; gr < ngr; ++gr) {
         for (int gc = 0; gc < ngc; ++gc) {
@@ -578,15 +657,9 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
             }
             const bool tailA = SIMPLE ? false : uniform(Mp > 128 ? 1 : 0) != 0;
             const bool full = nrm == 4 && ncm == 2;              // all eight main blocks live
-            const int Lw = 2 + (tailA ? 2 : 0) + nB;             // loads per stage of this wave
+            const int Lw = 2 + (tailA ? 2 : 0) + nB;             // DMA loads per stage of this wave
             // every wave has left the previous pass's buffers
             lds_barrier();
-            // k = K - 1 of each B column when K is odd (issued first: the stage waits cover it)
-            double fix = 0.0;
-            if (oddK && (int)threadIdx.x < Np) {
-                const int64_t idx = (int64_t)(n0 + threadIdx.x) * ldb + (K - 1);
-                fix = COL ? ld_dev(vB, idx) : ldg(Bop + idx);
-            }
             // the target's blocks go straight into the accumulators (issued first, so that they,
             // the first two operand stages and the scale decision share one round trip); the
             // product is then accumulated onto -2^shC C and the result is the negated sum
@@ -603,12 +676,20 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
                 accx[x] = zero4();
                 if (x < nxw) load_target_raw(accx[x], vC, P.ldc, m0, Mp, n0, Np, xr[x], xc[x]);
             }
-            dma_stage<PA, PB>(L, 0, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np, 0, K);
-            if (nkc > 1) dma_stage<PA, PB>(L, 1, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np, kUK, K);
+            // stages in flight and their odd-K values (one per ring parity)
+            IssueCursor is;
+            cursor_start(is, g, term);
+            double fx0 = 0.0, fx1 = 0.0;
+            for (int c = 0; c < 2 && c < nkc; ++c) {
+                const UpdTerm tm = is.term();
+                term_stage<KIND>(L, c, tm, m0, Mp, tailA, n0, Np, is.kc);
+                if (uniform((tm.K & 1) && is.kc + kUK >= tm.K ? 1 : 0)) {
+                    if (c == 0) fx0 = term_fix(tm, n0, Np); else fx1 = term_fix(tm, n0, Np);
+                }
+                cursor_next(is, g, term);
+            }
             if (!decided) {
-                const int2 d = decide();
-                shC = uniform(d.x);
-                shY = uniform(d.y);
+                shC = uniform(decide());
                 decided = true;
             }
 #pragma unroll
@@ -619,26 +700,36 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
 #pragma unroll
             for (int x = 0; x < 3; ++x) accx[x] = neg_scale4_masked(accx[x], shC, m0, Mp, n0, Np, xr[x], xc[x]);
             if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[2] = wall_clock64();
+            ProcCursor ps;
+            cursor_start(ps, g, term);
             for (int c = 0; c < nkc; ++c) {
                 const int buf = c % kDStages;
                 wait_vm(c + 1 < nkc ? Lw : 0);
                 lds_barrier();
-                const bool last = c == nkc - 1;
+                const int shY = uniform(ps.shY);
+                const bool pcol = KIND == 0 ? ps.col != 0 : KIND == 1;
+                const bool lastodd = uniform((ps.K & 1) && ps.kc + kUK >= ps.K ? 1 : 0) != 0;
                 if (shY != 0) {
                     // the solved tile enters the product times 2^shY (Algorithm 3's delta / alpha)
-                    double *sh = COL ? dstage_B(L, buf) : dstage_A(L, buf);
-                    const int cnt = COL ? kDB : kDA;
+                    double *sh = pcol ? dstage_B(L, buf) : dstage_A(L, buf);
+                    const int cnt = pcol ? kDB : kDA;
                     for (int t = threadIdx.x; t < cnt; t += kThreads) sh[t] = ldexp(sh[t], shY);
-                    if (last && oddK) lds_barrier();
+                    if (lastodd) lds_barrier();
                 }
-                if (last && oddK) {
+                if (lastodd) {
+                    const double fix = (c & 1) ? fx1 : fx0;
                     if ((int)threadIdx.x < Np)
-                        dstage_B(L, buf)[threadIdx.x * kBS + (K - 1 - kUK * c)] = (COL && shY) ? ldexp(fix, shY) : fix;
+                        dstage_B(L, buf)[threadIdx.x * kBS + (ps.K - 1 - ps.kc)] = (pcol && shY) ? ldexp(fix, shY) : fix;
                 }
-                if (shY != 0 || (last && oddK)) lds_barrier();
-                if (c + 2 < nkc)
-                    dma_stage<PA, PB>(L, (c + 2) % kDStages, Aop, lda, m0, Mp, tailA, Bop, ldb, n0, Np,
-                                      kUK * (c + 2), K);
+                if (shY != 0 || lastodd) lds_barrier();
+                if (c + 2 < nkc) {
+                    const UpdTerm tn = is.term();
+                    term_stage<KIND>(L, (c + 2) % kDStages, tn, m0, Mp, tailA, n0, Np, is.kc);
+                    if (uniform((tn.K & 1) && is.kc + kUK >= tn.K ? 1 : 0)) {
+                        if (c & 1) fx1 = term_fix(tn, n0, Np); else fx0 = term_fix(tn, n0, Np);
+                    }
+                    cursor_next(is, g, term);
+                }
                 const double *As = dstage_A(L, buf), *Bs = dstage_B(L, buf);
                 // this lane's 4 k of each of its B column blocks are adjacent: two 16-byte reads
                 double bq[2][4];
@@ -684,6 +775,7 @@ __device__ __forceinline__ void update_passes_f64(const Plan &P, const double *A
                                 accx[x] = mfma16(Bs[(16 * xc[x] + r) * kBS + k], As[k * kUS + 16 * xr[x] + r], accx[x]);
                     }
                 }
+                cursor_next(ps, g, term);
             }
             if (ustamp && threadIdx.x == 0 && gr == 0 && gc == 0) ustamp[3] = wall_clock64();
 #pragma unroll
@@ -753,14 +845,16 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
     if (gemm && !(P.flags & kFlagF32Updates)) {
         // FP64: the decision runs inside, overlapped with the first operand stages
         int shY = 0;
-        auto dec = [&]() -> int2 { const int2 d = decide(); shC = d.x; shY = d.y; return d; };
-        const bool simple = uniform(nrb == 8 && ((cols + 15) >> 4) == 8 && !(K & 1) ? 1 : 0) != 0;
+        const UpdTerm one{uniptr(Aop), uni64(lda_), uniptr(Bop), uni64(ldb_), K, colu ? 1 : 0, 0};
+        auto term = [&](int) -> UpdTerm { UpdTerm x = one; x.shY = shY; return x; };
+        auto dec = [&]() -> int { const int2 d = decide(); shC = d.x; shY = d.y; return d.x; };
+        const bool simple = uniform(nrb == 8 && ((cols + 15) >> 4) == 8 ? 1 : 0) != 0;
         if (colu) {
-            if (simple) update_passes_f64<true, true>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
-            else update_passes_f64<true, false>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+            if (simple) update_stream_f64<true, 1>(P, 1, term, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+            else update_stream_f64<false, 1>(P, 1, term, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
         } else {
-            if (simple) update_passes_f64<false, true>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
-            else update_passes_f64<false, false>(P, Aop, lda_, Bop, ldb_, K, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+            if (simple) update_stream_f64<true, 2>(P, 1, term, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+            else update_stream_f64<false, 2>(P, 1, term, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
         }
     } else {
         const int2 d = decide();
@@ -811,6 +905,169 @@ __device__ __noinline__ void run_update(const Plan &Pin, int kind_, int T_, int 
     if (threadIdx.x == 0) {
         tile_norm_store(P, T, u + 1, slab, best);
         tile_exp_store(P, T, u + 1, enew);
+    }
+    if (ustamp && threadIdx.x == 0) ustamp[5] = wall_clock64();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Multi-term update task: the g consecutive updates u0 .. u0 + g - 1 of target T (sources in the
+// order of update_index) applied in one pass,
+//     D = 2^shC C - sum_t 2^shY_t Aop_t Bop_t,
+// with Aop_t Bop_t = A_ik Y_kl (column source) or Y_ij B_jl (row source).  One scale decision
+// covers all terms: every operand is first brought to the common exponent emax (the largest of
+// the target's and the solved tiles'), then the smallest s >= 0 with
+//     2^-s (||C|| 2^(eC-emax) + sum_t ||A_t|| ||Y_t|| 2^(eY_t-emax)) <= OMEGA
+// is chosen (ProtectUpdate of Algorithm 3 with the sum of the terms' bounds, which bounds every
+// partial sum of the product as well), so that D = 2^-(emax+s) times the updated block.  The
+// K dimensions of the terms are concatenated into one stream of 16-k stages; the target is
+// read and written once.  Runs as one workgroup over the whole tile (one slab).
+// ---------------------------------------------------------------------------------------------
+
+// Sum over a 512-thread workgroup; every thread receives the result.  Two barriers.
+__device__ __forceinline__ double wg_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int i = 1; i < kWaves; ++i) r += red[i];
+    __syncthreads();
+    return r;
+}
+
+__device__ __noinline__ void run_update_group(const Plan &Pin, int T_, int u0_, int g_, UpdateLds &L,
+                                             uint64_t *ustamp)
+{
+    const Plan P = uniform_plan(Pin);
+    if (ustamp && threadIdx.x == 0) ustamp[0] = wall_clock64();
+    const int T = uniform(T_), u0 = uniform(u0_), g = uniform(g_);
+    const int ti = T / P.qt, tl = T % P.qt;
+    const int r0 = uniform(P.rowoff[ti]), rows = uniform(P.rowoff[ti + 1]) - r0;
+    const int c0 = uniform(P.coloff[tl]), cols = uniform(P.coloff[tl + 1]) - c0;
+    // the term table, with each term's share of the scale decision (gsh holds the solved tile's
+    // exponent until the decision replaces it by the shift)
+    const int t = threadIdx.x;
+    if (t < g) {
+        int ks, ls;
+        update_source(P.pt, ti, tl, u0 + t, &ks, &ls);
+        const int S = ks * P.qt + ls;
+        const bool col = ls == tl;
+        const int k0 = col ? P.rowoff[ks] : P.coloff[ls];
+        L.gS[t] = S;
+        L.gk0[t] = k0;
+        L.gK[t] = (col ? P.rowoff[ks + 1] : P.coloff[ls + 1]) - k0;
+        L.gcol[t] = col ? 1 : 0;
+        const int VS = tile_updates(P, S) + 1;
+        L.gsh[t] = tile_exp_at(P, S, VS);
+        L.gyn[t] = tile_norm_at(P, S, VS);
+        L.gtn[t] = col ? P.anorm[(size_t)ti * P.pt + ks] : P.bnorm[(size_t)ls * P.qt + tl];
+    }
+    const int eC = uniform(tile_exp_at(P, T, u0));
+    const double cn = unid(tile_norm_at(P, T, u0));
+    for (int i = threadIdx.x; i < kWaves * (kMaxTile + 3); i += kThreads) (&L.rs[0][0])[i] = 0.0;
+    __syncthreads();
+    if ((P.flags & kFlagF32Updates) || rows <= 0 || cols <= 0) {
+        // the FP32 form (and an empty target): the terms one after another
+        for (int s = 0; s < g; ++s) {
+            const int kind = uniform(L.gcol[s]) ? kTaskColUpdate : kTaskRowUpdate;
+            run_update(P, kind, T, uniform(L.gS[s]), u0 + s, 0, L, ustamp);
+            // this term's stores (the tile, its norm and exponent) are visible to the next term
+            __builtin_amdgcn_s_waitcnt(0);
+            __threadfence();
+            __syncthreads();
+        }
+        return;
+    }
+    if (ustamp && threadIdx.x == 0) ustamp[1] = wall_clock64();
+    // (captures only the operand bases, so that the plan's fields need not stay live in the loop)
+    const double *Ab = P.A + r0, *Yc = P.C + (int64_t)c0 * P.ldc, *Yr = P.C + r0;
+    const double *Bb = P.B + (int64_t)c0 * P.ldb;
+    const int64_t lda = P.lda, ldc = P.ldc, ldb = P.ldb;
+    UpdateLds *Lp = &L;
+    auto term = [=](int s) -> UpdTerm {
+        UpdTerm x;
+        const int k0 = uniform(Lp->gk0[s]);
+        x.K = uniform(Lp->gK[s]);
+        x.col = uniform(Lp->gcol[s]);
+        x.shY = uniform(Lp->gsh[s]);
+        if (x.col) {
+            x.Aop = Ab + (int64_t)k0 * lda; x.lda = lda;
+            x.Bop = Yc + k0; x.ldb = ldc;
+        } else {
+            x.Aop = Yr + (int64_t)k0 * ldc; x.lda = ldc;
+            x.Bop = Bb + k0; x.ldb = ldb;
+        }
+        return x;
+    };
+    // the scale decision over all terms: common exponent, then the bound at that exponent
+    int enew = 0;
+    auto dec = [&]() -> int {
+        const int eY = t < g ? L.gsh[t] : 0;
+        const double yn = t < g ? L.gyn[t] : 0.0, tn = t < g ? L.gtn[t] : 0.0;
+        const int eYmax = (int)wg_max(t < g ? (double)eY : (double)eC, L.red);
+        const int emax = uniform(eYmax > eC ? eYmax : eC);
+        double m = 0.0;
+        int E = INT32_MIN;
+        if (t < g) {
+            const double ys = ldexp(yn, eY - emax);
+            if (tn != 0.0 && ys != 0.0) {
+                const int ea = ilogb(tn), ey = ilogb(ys);
+                m = ldexp(tn, -ea) * ldexp(ys, -ey);   // [1, 4)
+                E = ea + ey;
+            }
+        } else if (t == kThreads - 1) {
+            const double cs = ldexp(cn, eC - emax);
+            if (cs != 0.0) {
+                E = ilogb(cs);
+                m = ldexp(cs, -E);
+            }
+        }
+        const double Ed = wg_max(E == INT32_MIN ? -1.0e300 : (double)E, L.red);
+        int sh = 0;
+        if (uniform(Ed > -1.0e299 ? 1 : 0)) {
+            // sum_t m_t 2^(E_t - Es) <= 4 (g + 1): no overflow; the margin covers its rounding
+            const int Es = (int)Ed;
+            const double sum = wg_sum(m != 0.0 ? ldexp(m, E - Es) : 0.0, L.red) * (1.0 + 0x1p-40);
+            int cl = ilogb(sum);
+            if (sum != ldexp(1.0, cl)) cl += 1;
+            sh = cl + Es - 1022;
+            if (sh < 0) sh = 0;
+        }
+        enew = uniform(emax + sh);
+        if (t < g) L.gsh[t] = eY - enew;
+        // every wave reads the shifts (the stage cursor fetches them next): a wave that read a
+        // stale shift would take a different number of barriers in the stage loop
+        __syncthreads();
+        return eC - enew;
+    };
+    int rb_lo, rb_hi;
+    slab_rows(rows, 1, 0, &rb_lo, &rb_hi);
+    const int nrb = rb_hi - rb_lo;
+    double *Ct = P.C + (int64_t)c0 * P.ldc + r0;
+    const bool simple = uniform(nrb == 8 && ((cols + 15) >> 4) == 8 ? 1 : 0) != 0;
+    if (simple) update_stream_f64<true, 0>(P, g, term, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+    else update_stream_f64<false, 0>(P, g, term, Ct, rows, cols, rb_lo, nrb, L, ustamp, dec);
+    __syncthreads();
+    if (ustamp && threadIdx.x == 0) ustamp[4] = wall_clock64();
+    if (threadIdx.x == 0) {
+        // scaling events: every term of a group whose decision rescaled the target or a solved tile
+        bool scaled = eC != enew;
+        for (int s = 0; s < g; ++s) scaled = scaled || L.gsh[s] != 0;
+        if (scaled) atomicAdd(&P.stats[1], (unsigned)g);
+    }
+    double best = 0.0;
+    for (int i = threadIdx.x; i < rows; i += kThreads) {
+        double tot = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) tot += L.rs[ww][i];
+        best = fmax(best, tot);
+    }
+    best = wg_max(best, L.red);
+    if (threadIdx.x == 0) {
+        tile_norm_store(P, T, u0 + g, 0, best);
+        tile_exp_store(P, T, u0 + g, enew);
     }
     if (ustamp && threadIdx.x == 0) ustamp[5] = wall_clock64();
 }

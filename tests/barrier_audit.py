@@ -144,6 +144,32 @@ def spill_slots(body):
     return slots
 
 
+_NOWRITE = ("s_cbranch", "s_branch", "s_waitcnt", "s_barrier", "s_nop", "s_sleep", "s_setprio", "s_endpgm",
+            "s_store", "s_buffer_store", "s_dcache", "s_trap", "s_setpc", "s_swappc", "s_call", "s_cmp",
+            "s_bitcmp", "s_set_gpr_idx")
+
+
+def _sregs(reg):
+    """The 32-bit SGPR names a register operand covers ('s[4:5]' -> {'s4', 's5'})."""
+    m = re.match(r"^s\[(\d+):(\d+)\]$", reg)
+    if m:
+        return {f"s{i}" for i in range(int(m.group(1)), int(m.group(2)) + 1)}
+    return {reg} if re.match(r"^s\d+$", reg) else set()
+
+
+def _written_sregs(op, parts):
+    """SGPRs an instruction writes through its first operand (scalar ALU results, 64-bit compare
+    masks, lane reads); empty for stores, branches and the like."""
+    if len(parts) < 2:
+        return set()
+    if op.startswith("s_") and not op.startswith(_NOWRITE):
+        return _sregs(parts[1])
+    if op.startswith(("v_cmp", "v_readfirstlane", "v_readlane")) and (op.endswith("_e64") or "readlane" in op
+                                                                       or "readfirstlane" in op):
+        return _sregs(parts[1])
+    return set()
+
+
 def transfer(insns, state, findings, where, slots=None):
     st = tuple(state)
     anded = {}      # this block: s_and_b64 dst, <saved exec>, x  ->  dst: the saved exec register
@@ -151,6 +177,11 @@ def transfer(insns, state, findings, where, slots=None):
     for s in insns:
         parts = s.replace(",", " ").split()
         op = parts[0]
+        # a saved copy of exec is gone once its register is overwritten (the instruction's own
+        # effect on the state is applied below)
+        w = _written_sregs(op, parts)
+        if w:
+            st = tuple(e for e in st if not (e[0] == "mark" and _sregs(e[1]) & w))
         if op == "v_readlane_b32" and len(parts) >= 4 and slots is not None:
             src = slots.get((parts[2], parts[3]), set())
             if len(src) == 1:
@@ -186,6 +217,13 @@ def transfer(insns, state, findings, where, slots=None):
                 findings.append((where, s, narrowed))
         elif op == "s_or_saveexec_b64" and len(parts) > 2 and parts[2] == "-1":
             st = _push(st, "mark", parts[1])     # whole-wave section (a register spill): exec saved
+        elif op in ("s_andn2_saveexec_b64", "s_or_saveexec_b64") and len(parts) > 2 \
+                and _find(st, parts[2]) >= 0 and st[_find(st, parts[2])][0] == "narrow":
+            # the other arm of an if/else: the source holds that arm's lanes (see the s_xor_b64
+            # rule below), the destination saves the lanes of the arm just run, and
+            # `s_or_b64 exec, exec, dst` after the other arm closes the whole if/else
+            i = _find(st, parts[2])
+            st = st[:i] + (("narrow", parts[1]),) + st[i + 1:]
         elif op in ("s_and_saveexec_b64", "s_andn2_saveexec_b64", "s_or_saveexec_b64", "s_xor_saveexec_b64"):
             st = _push(st, "narrow", parts[1])
         elif op == "s_or_b64" and len(parts) >= 4 and parts[1] == "exec" and parts[2] == "exec":

@@ -141,6 +141,37 @@ def test_growth_vs_oracle(T, orc, size, tile):
         _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2)
 
 
+@pytest.mark.parametrize("flags", [0, 4, 8])
+@pytest.mark.parametrize("m,n,tile", [(513, 260, 128), (1000, 700, 128), (300, 257, 64), (1056, 1056, 16)])
+def test_update_grouping_vs_oracle(T, orc, flags, m, n, tile):
+    """Tile updates one per task (default), same-front pairs as two-term updates (flag 4), and all
+    pending updates of a tile as one multi-term update (flag 8, left-looking; at m = n = 1056,
+    tile 16 the last tiles have 130 updates, more than one task holds): each matches the oracle,
+    element by element."""
+    A, B, C = W.separated_problem(77 + m + n, m, n, p2x2=0.25, upper_scale="sqrt")
+    Yo, eo, _ = orc.drsylv(A, B, C, 64)
+    Y, e, info = gpu_solve(T, A, B, C, tile=tile, flags=flags)
+    assert info == 0 and e == 0 and eo == 0
+    assert rel(Y, Yo) <= 1e-10 and maxrel(Y, Yo) <= 1e-10, (rel(Y, Yo), maxrel(Y, Yo))
+    assert orc.relres(A, B, Y, e, C) <= 1e-13
+
+
+@pytest.mark.parametrize("flags", [4, 8])
+@pytest.mark.parametrize("size", [384, 512])
+def test_grouped_updates_growth_vs_oracle(T, orc, flags, size):
+    """Growth inputs at tile 128, where the multi-term updates' one scale decision over all terms
+    rescales (every term's solved tile brought to the common exponent, then ProtectUpdate with the
+    sum of the terms' bounds)."""
+    A, B, C = W.config_growth(3, size, size)
+    Yo, eo, _ = orc.drsylv(A, B, C, 128)
+    Yo2, eo2, _ = orc.drsylv(A, B, C, 64)
+    Y, e, info, cnt = T.solve(A, B, C, tile=128, flags=flags, counters=True)
+    print(f"  gpu solve growth m=n={size} tile 128 flags {flags}: {cnt}", flush=True)
+    Y = Y.cpu().numpy()
+    assert info == 0 and cnt["scaled_updates"] > 0
+    _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2)
+
+
 def test_growth_closed_form(T):
     """Unscaled substitution overflows; Y/alpha must equal the closed form of
     (A + nu I) y = 1 with A = mu I + strict upper ones (exact rational reference)."""

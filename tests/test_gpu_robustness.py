@@ -88,16 +88,18 @@ def test_empty_source_tile_keeps_target_norm(T, orc):
     assert err <= 1e-8
 
 
+@pytest.mark.parametrize("flags", [0, 4])
 @pytest.mark.parametrize("m,n,tile", [(300, 257, 64), (513, 260, 128), (200, 170, 16)])
-def test_schedulers_are_bitwise_equal(T, m, n, tile):
+def test_schedulers_are_bitwise_equal(T, m, n, tile, flags):
     """Each target takes its updates in one fixed order and every reduction has a fixed order, so
-    the persistent DAG and the per-front launches produce identical bits."""
+    the persistent DAG and the per-front launches produce identical bits -- with one task per
+    update and with same-front pairs as two-term updates (flag 4), which both schedulers form."""
     for seed, gen in ((1, lambda s: W.separated_problem(s, m, n, p2x2=0.25)),
                       (2, lambda s: W.growth_problem(s, m, n))):
         A, B, C = gen(seed)
-        print(f"  gpu solve m={m} n={n} tile {tile} both schedulers seed {seed}", flush=True)
-        Yd, ed, infod = T.solve(A, B, C, tile=tile, scheduler="dag")
-        Yf, ef, infof = T.solve(A, B, C, tile=tile, scheduler="fronts")
+        print(f"  gpu solve m={m} n={n} tile {tile} flags {flags} both schedulers seed {seed}", flush=True)
+        Yd, ed, infod = T.solve(A, B, C, tile=tile, scheduler="dag", flags=flags)
+        Yf, ef, infof = T.solve(A, B, C, tile=tile, scheduler="fronts", flags=flags)
         assert (ed, infod) == (ef, infof)
         assert np.array_equal(Yd.cpu().numpy(), Yf.cpu().numpy())
 
