@@ -142,12 +142,14 @@ def test_growth_vs_oracle(T, orc, size, tile):
 
 
 @pytest.mark.parametrize("flags", [0, 4, 8])
-@pytest.mark.parametrize("m,n,tile", [(513, 260, 128), (1000, 700, 128), (300, 257, 64), (1056, 1056, 16)])
+@pytest.mark.parametrize("m,n,tile", [(513, 260, 128), (1000, 700, 128), (300, 257, 64), (1056, 1056, 16),
+                                      (600, 560, 256)])
 def test_update_grouping_vs_oracle(T, orc, flags, m, n, tile):
     """Tile updates one per task (default), same-front pairs as two-term updates (flag 4), and all
     pending updates of a tile as one multi-term update (flag 8, left-looking; at m = n = 1056,
     tile 16 the last tiles have 130 updates, more than one task holds): each matches the oracle,
-    element by element."""
+    element by element.  Tile 256 takes the update's multi-pass layout (up to 257 rows and
+    columns in passes of 9 x 9 blocks), tile 128 the single 8 x 8-block pass."""
     A, B, C = W.separated_problem(77 + m + n, m, n, p2x2=0.25, upper_scale="sqrt")
     Yo, eo, _ = orc.drsylv(A, B, C, 64)
     Y, e, info = gpu_solve(T, A, B, C, tile=tile, flags=flags)
