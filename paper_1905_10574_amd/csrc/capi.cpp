@@ -125,11 +125,12 @@ Layout make_layout(int64_t m, int64_t n, const Resolved &r)
 // blindly: a solve is weighted solve_cost() update units.
 // ------------------------------------------------------------------------------------------
 // Tile solve time over tile update time.  Measured on MI355X at tile 128: 0.44 ms per solve
-// against 48 us per update (ratio 9; weights 7.5 / 9 / 10.5 / 12 gave 74.9 / 72.3 / 73.0 /
-// 75.8 ms per solve at m = n = 8192).  The solve's length grows with tm + tn (leaf fronts), the
-// update's with tm tn k, so the ratio is scaled by (128 / tm) (128 / tn) for other tiles.
+// against 42 us per update (ratio 10.5).  Per solve at m = n = 8192, each weight run twice on
+// one box: 9 / 10.5 / 12 gave 74.2 / 72.7 / 74.9 ms, and on another 10 / 10.5 / 11 gave
+// 72.5 / 72.8 / 72.6-73.3 ms, so 10 is used.  The solve's length grows with tm + tn (leaf fronts), the update's with tm tn k, so the
+// ratio is scaled by (128 / tm) (128 / tn) for other tiles.
 #ifndef TRSYL_SOLVE_COST
-#define TRSYL_SOLVE_COST 9.0
+#define TRSYL_SOLVE_COST 10.0
 #endif
 double solve_cost(int tm, int tn)
 {
