@@ -52,6 +52,21 @@ def test_batched_bit_identical_to_single(T):
         assert torch.equal(Y.cpu(), Ys.cpu())
 
 
+@pytest.mark.parametrize("flags", [4, 8])
+def test_batched_grouped_updates_bit_identical_to_single(T, flags):
+    """The update-grouping options in the batched scheduler: each problem's result equals the single
+    solve's with the same tiles and option bit for bit (same multi-term tasks, same order per
+    target), and problems of both kinds keep eq. (9)."""
+    probs, tiles = _mixed()
+    out = T.solve_batched([p[0] for p in probs], [p[1] for p in probs], [p[2] for p in probs], tiles, flags=flags)
+    for (A, B, C), (tm, tn), (Y, e, info) in zip(probs, tiles, out):
+        Ys, es, infos = T.solve(A, B, C, tile=tm, tile_n=tn, flags=flags)
+        assert e == es and info == infos
+        assert torch.equal(Y.cpu(), Ys.cpu())
+        if C.size:
+            assert T.residual(A, B, Y, e, C) <= 1e-13
+
+
 def test_batched_parity_and_residual(T):
     probs, tiles = _mixed()
     out = T.solve_batched([p[0] for p in probs], [p[1] for p in probs], [p[2] for p in probs], tiles)
