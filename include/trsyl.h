@@ -30,7 +30,10 @@
  *           +-smin (lambda_A + lambda_B = 0 to working precision; Sec. 1 uniqueness
  *           condition); the result solves a nearby problem
  *        2  A or B is not upper quasi-triangular (two consecutive nonzero subdiagonals)
- *        3  non-finite input, or an input entry above OMEGA (precondition of Alg. 2/4)
+ *        3  non-finite input, an input entry above OMEGA, or a tile of A, B or C (in the
+ *           call's tiling, opts->tile_m / tile_n) whose infinity norm exceeds OMEGA: the data
+ *           requirement of Alg. 4 (entries at most OMEGA do not imply it; a finer tiling may
+ *           accept what a coarser one rejects)
  *        4  the persistent scheduler's watchdog expired (a dependency never resolved)
  *     On status 2 or 3 the contents of C are unspecified.
  *   - Functions are reentrant: concurrent calls need distinct workspaces.

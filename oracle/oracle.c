@@ -137,6 +137,19 @@ static double inf_norm(int64_t r, int64_t c, const double *M, int64_t ld)
     return best;
 }
 
+/* ||T||_inf of a square diagonal tile of a quasi-triangular matrix: only the entries on or above
+ * the first subdiagonal belong to the matrix. */
+static double quasi_inf_norm(int64_t r, const double *M, int64_t ld)
+{
+    double best = 0.0;
+    for (int64_t i = 0; i < r; ++i) {
+        double s = 0.0;
+        for (int64_t j = (i > 0 ? i - 1 : 0); j < r; ++j) s += fabs(EL(M, ld, i, j));
+        if (s > best) best = s;
+    }
+    return best;
+}
+
 static void scale_block(int64_t r, int64_t c, double *M, int64_t ld, long s)
 {
     if (s == 0) return;
@@ -523,7 +536,8 @@ static void update_row(tiled_t *T, int64_t k, int64_t j, int64_t l, double *tmp)
  * in the same tile row.  Finally alpha = min alpha_kl and each tile is rescaled to alpha.
  * The updates issued by one solved tile write disjoint tiles, so they may run in parallel
  * (nthreads > 1) without changing any result.  C (ld ldc) is overwritten with Y; e: alpha=2^-e.
- * Returns 0, 1 (a pivot was perturbed), 2 (bad structure), 3 (non-finite or > OMEGA input).
+ * Returns 0, 1 (a pivot was perturbed), 2 (bad structure), 3 (non-finite or > OMEGA input, or a
+ * tile of A, B or C whose infinity norm exceeds OMEGA).
  * ---------------------------------------------------------------------------------------- */
 int orc_drsylv(int64_t m, int64_t n, const double *A, int64_t lda, const double *B, int64_t ldb,
                double *C, int64_t ldc, int64_t tA, int64_t tB, int nthreads, int64_t *e_out)
@@ -572,6 +586,25 @@ int orc_drsylv(int64_t m, int64_t n, const double *A, int64_t lda, const double 
     for (int64_t k = 0; k < pt; ++k)
         for (int64_t l = 0; l < qt; ++l)
             T.ynorm[k * qt + l] = inf_norm(ro[k + 1] - ro[k], co[l + 1] - co[l], &EL(C, ldc, ro[k], co[l]), ldc);
+    /* The data requirement of Algorithm 4: every tile of A, B and C in this partition has
+     * infinity norm at most OMEGA.  Entries at most OMEGA do not imply it (a row sum runs over a
+     * tile's width of them), so the tile norms are checked as well. */
+    {
+        int bad = 0;
+        for (int64_t k = 0; k < pt; ++k) {
+            for (int64_t i = 0; i < k; ++i) bad |= !(T.anorm[i * pt + k] <= OMEGA);
+            bad |= !(quasi_inf_norm(ro[k + 1] - ro[k], &EL(A, lda, ro[k], ro[k]), lda) <= OMEGA);
+        }
+        for (int64_t j = 0; j < qt; ++j) {
+            for (int64_t l = 0; l < j; ++l) bad |= !(T.bnorm[l * qt + j] <= OMEGA);
+            bad |= !(quasi_inf_norm(co[j + 1] - co[j], &EL(B, ldb, co[j], co[j]), ldb) <= OMEGA);
+        }
+        for (int64_t t = 0; t < pt * qt; ++t) bad |= !(T.ynorm[t] <= OMEGA);
+        if (bad) {
+            free(ro); free(co); free(T.et); free(T.ynorm); free(T.anorm); free(T.bnorm);
+            return ORC_BAD_INPUT;
+        }
+    }
 
     int64_t tmax = 0;
     for (int64_t k = 0; k < pt; ++k) if (ro[k + 1] - ro[k] > tmax) tmax = ro[k + 1] - ro[k];

@@ -58,7 +58,9 @@ __global__ void k_structure(Plan P) { structure_body(P, blockIdx.x, gridDim.x); 
 
 // ||T_ik||_inf for a tile pair of the quasi-triangular matrix T (A or B); the diagonal tile also
 // feeds the global max |entry| and, for B, the 1-norm.  Entries below the first subdiagonal are
-// never read.  Non-finite or > OMEGA entries raise status 3.
+// never read.  Non-finite or > OMEGA entries raise status 3, and so does a tile norm above OMEGA
+// (Algorithm 4 requires every tile of A, B and C to have infinity norm at most OMEGA; entries at
+// most OMEGA do not imply it).
 __device__ void bound_tile(const Plan &P, const double *T, int64_t ld, const int32_t *off, int nt,
                            int i, int k, double *out, double *out1)
 {
@@ -79,6 +81,7 @@ __device__ void bound_tile(const Plan &P, const double *T, int64_t ld, const int
     }
     if (bad) set_status(P.status, kBadInput);
     best = wg_max(best, red);
+    if (threadIdx.x == 0 && !(best <= kOmega)) set_status(P.status, kBadInput);
     if (i == k) {
         mx = wg_max(mx, red);
         if (threadIdx.x == 0) atomic_max_nonneg(P.gmax, mx);
@@ -114,7 +117,7 @@ __device__ void bounds_B_body(const Plan &P, int b)
 __global__ void __launch_bounds__(kThreads) k_bounds_A(Plan P) { bounds_A_body(P, blockIdx.x); }
 __global__ void __launch_bounds__(kThreads) k_bounds_B(Plan P) { bounds_B_body(P, blockIdx.x); }
 
-// ||C_kl||_inf, input check, and version 0 of every tile's state.
+// ||C_kl||_inf, input checks (entries and the tile norm), and version 0 of every tile's state.
 __device__ void bounds_C_body(const Plan &P, int T)
 {
     if (plan_skipped(P)) return;
@@ -135,6 +138,7 @@ __device__ void bounds_C_body(const Plan &P, int T)
     if (bad) set_status(P.status, kBadInput);
     best = wg_max(best, red);
     if (threadIdx.x == 0) {
+        if (!(best <= kOmega)) set_status(P.status, kBadInput);   // Algorithm 4's data requirement
         tile_norm_store(P, T, 0, 0, best);
         for (int s = 1; s < P.slabs; ++s) tile_norm_store(P, T, 0, s, 0.0);
         tile_exp_store(P, T, 0, 0);

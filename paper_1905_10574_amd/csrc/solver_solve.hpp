@@ -363,9 +363,10 @@ __device__ __forceinline__ int leaf_exponent(const SolveLds &L, int I, int J, in
     const double t = ldexp(Tc, -64);
     int s = 0;
     if (b > t) {
-        s = ilogb(b) - ilogb(t);
-        if (s < 0) s = 0;
-        while (ldexp(b, -s) > t) ++s;
+        // start from the exponent difference when both are finite and nonzero; the loop is
+        // bounded whatever the values (2200 shifts take any double below any positive t)
+        if (t > 0.0 && b <= 0x1.fffffffffffffp1023) s = max(ilogb(b) - ilogb(t), 0);
+        while (s < 2200 && ldexp(b, -s) > t) ++s;
     }
     return emax + s;
 }
@@ -820,16 +821,22 @@ __device__ __noinline__ void run_solve(const Plan &Pin, int T_, double *scratch_
         const double dA = P.anorm[(size_t)ti * P.pt + ti];
         const double dB = P.bnorm[(size_t)tl * P.qt + tl];
         const double dB1 = P.bdiag1[tl];
-        const double Tc = unid(kOmega / (64.0 + 8.0 * (dA + dB1 + dB)));
+        // OMEGA / (64 + 8 (dA + dB1 + dB)), formed with every term halved (the same quotient,
+        // rounding included): with dA, dB <= OMEGA the sum overflows only if the 1-norm dB1 does,
+        // and then Tc = 0 keeps the speculative paths off
+        const double Tc = unid((kOmega * 0x1p-4) / (4.0 + ((0.5 * dA + 0.5 * dB1) + 0.5 * dB)));
         const DevView vY = dev_view(Y, P.ldc, mr, nc);
         int done = 0;
-        // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016
-        // (the magnitude test is made wave-uniform: both branches below enclose barriers).  A tile
+        // the unguarded small solves assume unscaled Kronecker entries: max|A|,|B| < 2^1016, and
+        // the certificate a bound of at least one (below it, tile norms within a few powers of two
+        // of OMEGA, values of order one would fail it or force the leaf-tiled solve to rescale;
+        // Algorithm 2 as printed needs no such margin).  The tests are made wave-uniform: both
+        // branches below enclose barriers.  A tile
         // whose updates already had to scale it (e_in > 0) goes straight to the leaf-tiled robust
         // solve: growth upstream predicts growth inside the tile, where the speculative attempt
         // would run several fronts before its certificate fails.  e_in is fixed by the update
         // order, so the choice (and the result) does not depend on timing.
-        const int spec = uniform(!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016 ? 1 : 0);
+        const int spec = uniform(!(P.flags & kFlagRobustSolve) && *P.gmax < 0x1p1016 && Tc >= 1.0 ? 1 : 0);
         const int try_fast = uniform(spec && e_in == 0 ? 1 : 0);
         if (try_fast)
             done = uniform(tile_solve_fast(P, Ad, Bd, vY, scratch, mr, nc, smin, Tc, L, stamp));

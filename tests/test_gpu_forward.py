@@ -174,6 +174,45 @@ def test_grouped_updates_growth_vs_oracle(T, orc, flags, size):
     _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2)
 
 
+def test_tile_norm_precondition_vs_oracle(T, orc):
+    """Algorithm 4's data requirement bounds tile norms by Omega, not entries: the same tiling is
+    rejected (status 3) or accepted on both sides.  Upper-triangular A entries just below 2^1016
+    fail 128-wide tiles and pass 64 and 16-wide ones (row sums near 2^1022 - 2^1020: the
+    speculative tile solve's certificate bound falls below one there, so Algorithm 2 runs on
+    every tile); C entries up to 2^1020 over 8 columns fail 16-wide tiles, 2^1018 pass them."""
+    rng = np.random.default_rng(5)
+    m, n = 128, 4
+    A = np.triu(rng.uniform(0.9, 1, (m, m))) * 2.0 ** 1016
+    B = np.triu(rng.uniform(0.5, 1, (n, n)))
+    C = rng.uniform(-1, 1, (m, n))
+    assert orc.drsylv(A, B, C, 128)[2] == 3
+    for sched in ("dag", "fronts"):
+        _, _, info = gpu_solve(T, A, B, C, tile=128, scheduler=sched)
+        assert info == 3
+    for t in (64, 16):
+        Yo, eo, rco = orc.drsylv(A, B, C, t)
+        assert rco == 0 and eo == 0
+        for sched in ("dag", "fronts"):
+            Y, e, info = gpu_solve(T, A, B, C, tile=t, scheduler=sched)
+            assert info == 0 and e == 0
+            assert maxrel(Y, Yo) <= 1e-10, (t, sched, maxrel(Y, Yo))
+    A2 = np.triu(rng.uniform(0.5, 1, (64, 64))) + 4 * np.eye(64)
+    B2 = 2 * np.eye(8) + np.triu(rng.uniform(0, 0.5, (8, 8)), 1)
+    for ec, want in ((1020, 3), (1018, 0)):
+        C2 = np.ldexp(rng.uniform(0.5, 1, (64, 8)), ec)
+        C2[::7, :] = 2.0 ** ec
+        Yo, eo, rco = orc.drsylv(A2, B2, C2, 16)
+        Y, e, info = gpu_solve(T, A2, B2, C2, tile=16)
+        assert rco == want and info == want
+        if want == 0:
+            assert np.isfinite(Y).all() and np.abs(Y).max() <= OMEGA
+            assert orc.relres(A2, B2, Y, e, C2) <= 1e-13
+            ng, sg = normalised(Y)
+            no, so = normalised(Yo)
+            assert abs((sg + e) - (so + eo)) <= 1
+            assert rel(np.ldexp(ng, (sg + e) - (so + eo)), no) <= 1e-10
+
+
 def test_growth_closed_form(T):
     """Unscaled substitution overflows; Y/alpha must equal the closed form of
     (A + nu I) y = 1 with A = mu I + strict upper ones (exact rational reference)."""

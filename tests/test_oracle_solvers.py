@@ -263,6 +263,34 @@ def test_input_errors(orc):
     assert orc.drsylv(np.array([[1.0]]), np.array([[-1.0]]), np.ones((1, 1)))[2] == orc.RC_PERTURBED
 
 
+def test_tile_norm_precondition(orc):
+    """Algorithm 4's data requirement (Sec. 2.2) bounds the infinity norms of the tiles of A, B and
+    C by Omega, not their entries.  Upper-triangular entries just below 2^1016 have 128-wide row
+    sums near 2^1023 (rc 3 at tile 128) and 64-wide ones near 2^1022 - 2^1020 (accepted at tiles 64
+    and 16, with the solution of the Kronecker system of the problem scaled by 2^-1016).  C entries
+    up to 2^1020 over 8 columns fail 16-wide tiles (row sums up to 2^1023) and pass 4-wide ones."""
+    rng = np.random.default_rng(5)
+    m, n = 128, 4
+    A = np.triu(rng.uniform(0.9, 1, (m, m))) * 2.0 ** 1016
+    B = np.triu(rng.uniform(0.5, 1, (n, n)))
+    C = rng.uniform(-1, 1, (m, n))
+    assert np.abs(A).max() <= OMEGA and orc.drsylv(A, B, C, 128)[2] == orc.RC_BAD_INPUT
+    s = 2.0 ** -1016
+    K = np.kron(np.eye(n), A * s) + np.kron((B * s).T, np.eye(m))
+    X = np.linalg.solve(K, (C * s).reshape(-1, order="F")).reshape((m, n), order="F")
+    for t in (64, 16):
+        Y, e, rc = orc.drsylv(A, B, C, t)
+        assert rc == 0 and e == 0
+        assert np.abs(Y - X).max() <= 1e-12 * np.abs(X).max()
+    A2 = np.triu(rng.uniform(0.5, 1, (64, 64))) + 4 * np.eye(64)
+    B2 = 2 * np.eye(8) + np.triu(rng.uniform(0, 0.5, (8, 8)), 1)
+    C2 = np.ldexp(rng.uniform(0.5, 1, (64, 8)), 1020)
+    C2[::7, :] = 2.0 ** 1020
+    assert orc.drsylv(A2, B2, C2, 16)[2] == orc.RC_BAD_INPUT
+    Y, e, rc = orc.drsylv(A2, B2, C2, 4)
+    assert rc == 0 and np.isfinite(Y).all() and orc.relres(A2, B2, Y, e, C2) <= 1e-15
+
+
 @pytest.mark.parametrize("m,n", [(5, 4), (12, 9), (20, 20)])
 def test_adjoint_matches_kronecker_transpose(orc, m, n):
     A, B, C = W.separated_problem(m * n, m, n, p2x2=0.3, upper_scale="none")
