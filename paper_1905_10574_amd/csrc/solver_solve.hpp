@@ -228,11 +228,22 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
     const int64_t lds = mr;
     LeafLds &LL = L.leaf[w];
     int ok = 1;
-    for (int d = 0; d < nla + nlb - 1; ++d) {
+    const int nfr = nla + nlb - 1;
+    // Early partial sums.  On a narrow front the waves without a leaf compute, while the leaves
+    // are solved, the part of each next-front leaf's right-hand-side GEMM that reads leaves solved
+    // on earlier fronts (rows below the neighbour below, columns left of the neighbour to the
+    // left) into partial slots kWaves + 5 (d & 1) + leaf; the next front's GEMM phase then only
+    // reads its two neighbours, solved on the front just finished.  Slots below kWaves hold the
+    // GEMM phase's partials of the current front (at most kWaves of them on a narrow front).
+    int early = 0, ebase = kWaves;
+    for (int d = 0; d < nfr; ++d) {
         const int jlo = d - (nla - 1) > 0 ? d - (nla - 1) : 0;
         const int jhi = d < nlb - 1 ? d : nlb - 1;
         const int nleaf = jhi - jlo + 1;
-        const int parts = nleaf >= kWaves ? 1 : kWaves / nleaf;
+        const int use_early = uniform(early);
+        // the GEMM phase's items per leaf, their slots li * parts + p
+        const int split = use_early && 2 * nleaf <= kWaves ? 1 : 0;      // neighbour terms apart
+        const int parts = use_early ? 1 + split : (nleaf >= kWaves ? 1 : kWaves / nleaf);
         double rhs[4];
         if (w < nleaf) leaf_inputs(P, Ad, Bd, Y, L, LL, nla - 1 - (d - (jlo + w)), jlo + w, rhs);
         // phase A: partial right-hand-side GEMMs, work item = leaf * parts + part
@@ -242,20 +253,30 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
             const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
             const int kb = L.la[I + 1];
-            const int K1 = mr - kb, K2 = lc0;               // rows below, columns left
-            const int nch = (K1 + 15) / 16 + (K2 + 15) / 16;
-            const int c0 = (int)(((int64_t)part * nch) / parts), c1 = (int)(((int64_t)(part + 1) * nch) / parts);
-            const int n1 = (K1 + 15) / 16;                  // chunks of the first term
             d4 acc = zero4();
-            // first term: A(I, below) Y(below, J), chunks [c0, min(c1, n1))
-            if (c0 < n1)
-                leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
-                          lds, ncl, 16 * c0, c1 < n1 ? 16 * c1 : K1);
-            // second term: Y(I, left) B(left, J), chunks [max(c0, n1), c1) shifted by n1
-            if (c1 > n1) {
-                const int s0 = (c0 > n1 ? c0 : n1) - n1, s1 = c1 - n1;
-                leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 16 * s0,
-                          16 * s1 < K2 ? 16 * s1 : K2);
+            if (use_early) {
+                // the neighbour below (rows of leaf I + 1) and the one to the left (columns of
+                // leaf J - 1), both solved on front d - 1; with split, one per item
+                if ((!split || part == 0) && I + 1 < nla)
+                    leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
+                              lds, ncl, 0, L.la[I + 2] - kb);
+                if ((!split || part == 1) && J > 0)
+                    leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, L.lb[J - 1], lc0);
+            } else {
+                const int K1 = mr - kb, K2 = lc0;               // rows below, columns left
+                const int nch = (K1 + 15) / 16 + (K2 + 15) / 16;
+                const int c0 = (int)(((int64_t)part * nch) / parts), c1 = (int)(((int64_t)(part + 1) * nch) / parts);
+                const int n1 = (K1 + 15) / 16;                  // chunks of the first term
+                // first term: A(I, below) Y(below, J), chunks [c0, min(c1, n1))
+                if (c0 < n1)
+                    leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
+                              lds, ncl, 16 * c0, c1 < n1 ? 16 * c1 : K1);
+                // second term: Y(I, left) B(left, J), chunks [max(c0, n1), c1) shifted by n1
+                if (c1 > n1) {
+                    const int s0 = (c0 > n1 ? c0 : n1) - n1, s1 = c1 - n1;
+                    leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 16 * s0,
+                              16 * s1 < K2 ? 16 * s1 : K2);
+                }
             }
             double *pp = L.part[item];
 #pragma unroll
@@ -263,6 +284,15 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
         }
         __syncthreads();
         TRSYL_STAMP(stamp, 4 + 2 * d);
+        // the next front's early partials, when this front leaves enough waves without a leaf
+        // (each takes at most two next-front leaves) and the next front is narrow
+        const int d1 = d + 1;
+        const int jlo1 = d1 - (nla - 1) > 0 ? d1 - (nla - 1) : 0;
+        const int jhi1 = d1 < nlb - 1 ? d1 : nlb - 1;
+        const int nleaf1 = d1 < nfr ? jhi1 - jlo1 + 1 : 0;
+        const int idle = nleaf < kWaves ? kWaves - nleaf : 0;
+        const int next_early = uniform(nleaf1 > 0 && nleaf1 <= 5 && nleaf <= 5 && 2 * idle >= nleaf1 ? 1 : 0);
+        const int nbase = kWaves + 5 * (d1 & 1);
         // phase B: wave k takes leaves k, k + 8, ...: fills its buffer with the leaf's right-hand
         // side minus the partial sums (added in order), solves the leaf and stores it to S.
         for (int li = w; li < nleaf; li += kWaves) {
@@ -278,6 +308,7 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
                 if (mm < nr && nn < ncl) {
                     double g = 0.0;
                     for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
+                    if (use_early) g += L.part[ebase + li][nn * kLd + mm];
                     v = rhs[i] - g;
                     if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
                 }
@@ -296,10 +327,31 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
                 if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
             }
         }
+        if (next_early && w >= nleaf) {
+            // the ranges solved on fronts up to d - 1: rows from leaf I + 2 on, columns before
+            // leaf J - 1 (the earlier front's slots, ebase, are being read above: the other set)
+            for (int it = w - nleaf; it < nleaf1; it += idle) {
+                const int J = jlo1 + it, I = nla - 1 - (d1 - J);
+                const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
+                const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
+                const int kb = L.la[I + 1];
+                d4 acc = zero4();
+                if (I + 1 < nla)
+                    leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
+                              lds, ncl, L.la[I + 2] - kb, mr - kb);
+                if (J > 0)
+                    leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 0, L.lb[J - 1]);
+                double *pp = L.part[nbase + it];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pp[((lane >> 4) + 4 * i) * kLd + (lane & 15)] = acc[i];
+            }
+        }
         if (!ok) L.fail = 1;
         __threadfence_block();
         __syncthreads();
         TRSYL_STAMP(stamp, 5 + 2 * d);
+        early = next_early;
+        ebase = nbase;
         if (uniform(L.fail)) break;
     }
     asm volatile("" ::"v"(warm));

@@ -115,6 +115,21 @@ def test_batched_isolates_bad_problem(T):
         assert T.residual(A, B, Y, e, C) <= 1e-13
 
 
+def test_batched_isolates_tile_norm_violation(T):
+    """A problem whose C has 32-wide tile rows summing past Omega (entries 2^1020, each at most
+    Omega) fails Algorithm 4's data requirement: status 3 for it alone, as in the oracle."""
+    A1, B1, C1 = W.separated_problem(1, 80, 70)
+    A2, B2, C2 = W.separated_problem(2, 60, 50)
+    C2 = np.full_like(C2, 2.0 ** 1020)
+    A3, B3, C3 = W.separated_problem(3, 100, 40)
+    assert oracle.drsylv(A2, B2, C2, 32)[2] == 3
+    out = T.solve_batched([A1, A2, A3], [B1, B2, B3], [C1, C2, C3], [(32, 32)] * 3)
+    assert out[1][2] == 3
+    for (A, B, C), (Y, e, info) in (((A1, B1, C1), out[0]), ((A3, B3, C3), out[2])):
+        assert info == 0 and e == 0
+        assert T.residual(A, B, Y, e, C) <= 1e-13
+
+
 def test_autotuner_table(T, tmp_path):
     """The tuner ranks the candidates by the median of its timed runs on a batch that mixes
     separated and growth problems, and writes the table (with the medians) as JSON."""

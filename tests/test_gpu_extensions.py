@@ -54,6 +54,25 @@ def test_adjoint_matches_oracle(T, m, n, tile):
     assert np.linalg.norm(R) / (np.linalg.norm(Wm) + (np.linalg.norm(A) + np.linalg.norm(B)) * np.linalg.norm(G)) <= 1e-13
 
 
+def test_adjoint_tile_norm_precondition(T):
+    """The adjoint runs Algorithm 4 on the order-reversed problem, whose tiles carry its data
+    requirement (tile infinity norms at most Omega): upper-triangular entries just below 2^1016
+    fail 128-wide tiles and pass 64-wide ones, with the oracle's adjoint in the same tiling."""
+    rng = np.random.default_rng(6)
+    m, n = 128, 4
+    A = np.triu(rng.uniform(0.9, 1, (m, m))) * 2.0 ** 1016
+    B = np.triu(rng.uniform(0.5, 1, (n, n)))
+    Wm = rng.uniform(-1, 1, (m, n))
+    assert oracle.adjoint(A, B, Wm, 128)[2] == 3
+    _, _, info = T.adjoint(A, B, Wm, tile=128)
+    assert info == 3
+    Go, eo, rc = oracle.adjoint(A, B, Wm, 64)
+    G, e, info = T.adjoint(A, B, Wm, tile=64)
+    assert rc == 0 and info == 0 and e == 0 and eo == 0
+    G = G.cpu().numpy()
+    assert np.abs(G - Go).max() <= 1e-10 * np.abs(Go).max()
+
+
 def test_adjoint_empty(T):
     A = np.zeros((0, 0))
     B = np.eye(3)
