@@ -35,7 +35,11 @@ namespace trsyl {
 #define TRSYL_STAMP(ptr, idx) do { (void)(ptr); } while (0)
 #endif
 
-constexpr int kMaxParts = kMaxLeaves > kWaves ? kMaxLeaves : kWaves;
+// Partial-sum slots: the GEMM phase's items of the current front (at most max(kWaves, leaves),
+// at most kEarlySet when the front takes part in early partials), then two sets of kEarlySet
+// slots for the early partials of the next front (see tile_solve_fast).
+constexpr int kEarlySet = 9;
+constexpr int kMaxParts = kMaxLeaves > 3 * kEarlySet ? kMaxLeaves : 3 * kEarlySet;
 
 struct SolveLds {
     LeafLds leaf[kWaves];
@@ -44,6 +48,7 @@ struct SolveLds {
     int la[kMaxLeaves + 1], lb[kMaxLeaves + 1];
     int nla, nlb;
     int fail;
+    int ectr;            // next early-partial item (an LDS work counter)
     int tguess, tnext;   // leaf-tiled solve: growth shift to start from, and this front's largest
     union {
         struct {   // Algorithm 2 on the whole tile
@@ -161,6 +166,54 @@ __device__ __forceinline__ void leaf_gemm(d4 &acc, const double *Aop, int64_t ld
     }
 }
 
+// Two GEMM terms of at most 16 k each, A1 B1 over k in [0, k1) and A2 B2 over k in [k20, k21),
+// added to acc with all their loads issued before the first MFMA (one memory round trip).  A term
+// with an empty range issues no load.  Operand layouts as in leaf_gemm.
+__device__ __forceinline__ void leaf_gemm_pair(d4 &acc, const double *A1, int64_t lda1, const double *B1,
+                                               int64_t ldb1, int k1, const double *A2, int64_t lda2,
+                                               const double *B2, int64_t ldb2, int k20, int k21, int nr, int ncl)
+{
+    const int lane = lane_here();
+    const int r = lane & 15, q = lane >> 4;
+    const bool va = r < nr, vb = r < ncl;
+    const int has1 = uniform(k1 > 0 ? 1 : 0), has2 = uniform(k21 > k20 ? 1 : 0);
+    double a1[4], b1[4], a2[4], b2[4];
+    if (has1) {
+        const double *Ar = A1 + (va ? r : 0);
+        const double *Bc = B1 + (int64_t)(vb ? r : 0) * ldb1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * q + j, kk = k < k1 ? k : 0;
+            a1[j] = ldg(Ar + (int64_t)kk * lda1);
+            b1[j] = ldg(Bc + kk);
+        }
+    }
+    if (has2) {
+        const double *Ar = A2 + (va ? r : 0);
+        const double *Bc = B2 + (int64_t)(vb ? r : 0) * ldb2;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k20 + 4 * q + j, kk = k < k21 ? k : k20;
+            a2[j] = ldg(Ar + (int64_t)kk * lda2);
+            b2[j] = ldg(Bc + kk);
+        }
+    }
+    if (has1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool kin = 4 * q + j < k1;
+            acc = mfma16((vb && kin) ? b1[j] : 0.0, (va && kin) ? a1[j] : 0.0, acc);
+        }
+    }
+    if (has2) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool kin = k20 + 4 * q + j < k21;
+            acc = mfma16((vb && kin) ? b2[j] : 0.0, (va && kin) ? a2[j] : 0.0, acc);
+        }
+    }
+}
+
 // Loads the inputs of leaf (I, J) that do not depend on other leaves: its diagonal blocks into
 // LL.Al / LL.Bl and its right-hand side into registers (lane (m, n0): entries (m, n0 + 4i)).
 __device__ __forceinline__ void leaf_inputs(const Plan &P, const double *Ad, const double *Bd,
@@ -229,13 +282,15 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
     LeafLds &LL = L.leaf[w];
     int ok = 1;
     const int nfr = nla + nlb - 1;
-    // Early partial sums.  On a narrow front the waves without a leaf compute, while the leaves
-    // are solved, the part of each next-front leaf's right-hand-side GEMM that reads leaves solved
-    // on earlier fronts (rows below the neighbour below, columns left of the neighbour to the
-    // left) into partial slots kWaves + 5 (d & 1) + leaf; the next front's GEMM phase then only
-    // reads its two neighbours, solved on the front just finished.  Slots below kWaves hold the
-    // GEMM phase's partials of the current front (at most kWaves of them on a narrow front).
-    int early = 0, ebase = kWaves;
+    // Early partial sums.  While a front's leaves are solved, every wave without a leaf left
+    // (at once when it has none) takes items from an LDS counter: a part of a next-front leaf's
+    // right-hand-side GEMM over the leaves solved on earlier fronts (rows below the neighbour
+    // below, columns left of the neighbour to the left), into the set of kEarlySet slots after
+    // the current front's.  The next front's GEMM phase then only reads its two neighbours,
+    // solved on the front just finished.  The two sets alternate by front parity: one is read
+    // while the other is written.  Fronts of more than kEarlySet leaves take no part.
+    int early = 0, ebase = kEarlySet, epe = 1;
+    if (threadIdx.x == 0) L.ectr = 0;
     for (int d = 0; d < nfr; ++d) {
         const int jlo = d - (nla - 1) > 0 ? d - (nla - 1) : 0;
         const int jhi = d < nlb - 1 ? d : nlb - 1;
@@ -257,11 +312,10 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
             if (use_early) {
                 // the neighbour below (rows of leaf I + 1) and the one to the left (columns of
                 // leaf J - 1), both solved on front d - 1; with split, one per item
-                if ((!split || part == 0) && I + 1 < nla)
-                    leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
-                              lds, ncl, 0, L.la[I + 2] - kb);
-                if ((!split || part == 1) && J > 0)
-                    leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, L.lb[J - 1], lc0);
+                const int kb1 = (!split || part == 0) && I + 1 < nla ? L.la[I + 2] - kb : 0;
+                const int kl0 = (!split || part == 1) && J > 0 ? L.lb[J - 1] : lc0;
+                leaf_gemm_pair(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, S + (int64_t)lc0 * lds + kb, lds, kb1,
+                               S + lr0, lds, Bd + (int64_t)lc0 * P.ldb, P.ldb, kl0, lc0, nr, ncl);
             } else {
                 const int K1 = mr - kb, K2 = lc0;               // rows below, columns left
                 const int nch = (K1 + 15) / 16 + (K2 + 15) / 16;
@@ -284,15 +338,14 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
         }
         __syncthreads();
         TRSYL_STAMP(stamp, 4 + 2 * d);
-        // the next front's early partials, when this front leaves enough waves without a leaf
-        // (each takes at most two next-front leaves) and the next front is narrow
+        // the next front's early partials: kEarlySet items at most, pe parts per leaf
         const int d1 = d + 1;
         const int jlo1 = d1 - (nla - 1) > 0 ? d1 - (nla - 1) : 0;
         const int jhi1 = d1 < nlb - 1 ? d1 : nlb - 1;
         const int nleaf1 = d1 < nfr ? jhi1 - jlo1 + 1 : 0;
-        const int idle = nleaf < kWaves ? kWaves - nleaf : 0;
-        const int next_early = uniform(nleaf1 > 0 && nleaf1 <= 5 && nleaf <= 5 && 2 * idle >= nleaf1 ? 1 : 0);
-        const int nbase = kWaves + 5 * (d1 & 1);
+        const int next_early = uniform(nleaf1 > 0 && nleaf1 <= kEarlySet && nleaf <= kEarlySet ? 1 : 0);
+        const int pe = next_early ? kEarlySet / nleaf1 : 1;
+        const int nbase = kEarlySet * (1 + (d1 & 1));
         // phase B: wave k takes leaves k, k + 8, ...: fills its buffer with the leaf's right-hand
         // side minus the partial sums (added in order), solves the leaf and stores it to S.
         for (int li = w; li < nleaf; li += kWaves) {
@@ -308,7 +361,8 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
                 if (mm < nr && nn < ncl) {
                     double g = 0.0;
                     for (int p = 0; p < parts; ++p) g += L.part[li * parts + p][nn * kLd + mm];
-                    if (use_early) g += L.part[ebase + li][nn * kLd + mm];
+                    if (use_early)
+                        for (int p = 0; p < epe; ++p) g += L.part[ebase + li * epe + p][nn * kLd + mm];
                     v = rhs[i] - g;
                     if (!(fabs(rhs[i]) <= Tc) || !(fabs(v) <= Tc)) ok = 0;
                 }
@@ -327,31 +381,50 @@ __device__ int tile_solve_fast(const Plan &P, const double *Ad, const double *Bd
                 if (mm < nr && nn < ncl) stg(S + (int64_t)(lc0 + nn) * lds + lr0 + mm, LL.R[nn * kLd + mm]);
             }
         }
-        if (next_early && w >= nleaf) {
-            // the ranges solved on fronts up to d - 1: rows from leaf I + 2 on, columns before
-            // leaf J - 1 (the earlier front's slots, ebase, are being read above: the other set)
-            for (int it = w - nleaf; it < nleaf1; it += idle) {
-                const int J = jlo1 + it, I = nla - 1 - (d1 - J);
+        if (next_early) {
+            // items it = leaf * pe + part over the ranges solved on fronts up to d - 1: rows from
+            // leaf I + 2 on, columns before leaf J - 1, in 16-k chunks split evenly over pe parts
+            for (;;) {
+                int it = 0;
+                if (lane == 0) it = atomicAdd(&L.ectr, 1);
+                it = __builtin_amdgcn_readfirstlane(it);
+                if (it >= nleaf1 * pe) break;
+                const int J = jlo1 + it / pe, part = it % pe;
+                const int I = nla - 1 - (d1 - J);
                 const int lr0 = L.la[I], nr = L.la[I + 1] - lr0;
                 const int lc0 = L.lb[J], ncl = L.lb[J + 1] - lc0;
                 const int kb = L.la[I + 1];
+                const int k1o = I + 1 < nla ? L.la[I + 2] - kb : 0, K1 = mr - kb;   // rows [k1o, K1)
+                const int K2 = J > 0 ? L.lb[J - 1] : 0;                            // columns [0, K2)
+                const int n1 = (K1 - k1o + 15) / 16;
+                const int nch = n1 + (K2 + 15) / 16;
+                const int c0 = (int)(((int64_t)part * nch) / pe), c1 = (int)(((int64_t)(part + 1) * nch) / pe);
                 d4 acc = zero4();
-                if (I + 1 < nla)
+                if (c0 < n1)
                     leaf_gemm(acc, Ad + (int64_t)kb * P.lda + lr0, P.lda, nr, S + (int64_t)lc0 * lds + kb,
-                              lds, ncl, L.la[I + 2] - kb, mr - kb);
-                if (J > 0)
-                    leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 0, L.lb[J - 1]);
-                double *pp = L.part[nbase + it];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) pp[((lane >> 4) + 4 * i) * kLd + (lane & 15)] = acc[i];
+                              lds, ncl, k1o + 16 * c0, c1 < n1 ? k1o + 16 * c1 : K1);
+                if (c1 > n1) {
+                    const int s0 = (c0 > n1 ? c0 : n1) - n1, s1 = c1 - n1;
+                    leaf_gemm(acc, S + lr0, lds, nr, Bd + (int64_t)lc0 * P.ldb, P.ldb, ncl, 16 * s0,
+                              16 * s1 < K2 ? 16 * s1 : K2);
+                }
+                // four stores written out: inside the work loop the compiler leaves a loop here
+                // rolled, with a dynamic index into the accumulator
+                double *pp = L.part[nbase + it] + (lane >> 4) * kLd + (lane & 15);
+                pp[0] = acc[0];
+                pp[4 * kLd] = acc[1];
+                pp[8 * kLd] = acc[2];
+                pp[12 * kLd] = acc[3];
             }
         }
         if (!ok) L.fail = 1;
         __threadfence_block();
         __syncthreads();
         TRSYL_STAMP(stamp, 5 + 2 * d);
+        if (threadIdx.x == 0) L.ectr = 0;   // read again only after the next front's barrier
         early = next_early;
         ebase = nbase;
+        epe = pe;
         if (uniform(L.fail)) break;
     }
     asm volatile("" ::"v"(warm));
