@@ -124,10 +124,10 @@ Layout make_layout(int64_t m, int64_t n, const Resolved &r)
 // update_index()).  The simulation's durations matter because the kernel follows the order
 // blindly: a solve is weighted solve_cost() update units.
 // ------------------------------------------------------------------------------------------
-// Tile solve time over tile update time.  Measured on MI355X at tile 128: 0.44 ms per solve
-// against 42 us per update (ratio 10.5).  Per solve at m = n = 8192, each weight run twice on
-// one box: 9 / 10.5 / 12 gave 74.2 / 72.7 / 74.9 ms, and on another 10 / 10.5 / 11 gave
-// 72.5 / 72.8 / 72.6-73.3 ms, so 10 is used.  The solve's length grows with tm + tn (leaf fronts), the update's with tm tn k, so the
+// Tile solve time over tile update time.  Measured on MI355X at tile 128: 0.40 ms per solve
+// against 42 us per update (ratio 9.5).  Per solve at m = n = 8192 on one box: 8.5 / 9 / 9.5 /
+// 10 / 11 gave 71.0 / 70.5 / 69.9 / 69.5 / 70.3 ms (the middle three and 10 twice each, within
+// 0.05 ms), so 10 is used.  The solve's length grows with tm + tn (leaf fronts), the update's with tm tn k, so the
 // ratio is scaled by (128 / tm) (128 / tn) for other tiles.
 #ifndef TRSYL_SOLVE_COST
 #define TRSYL_SOLVE_COST 10.0
