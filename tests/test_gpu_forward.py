@@ -5,11 +5,13 @@ Gates (from the method's contract and the solve's error analysis):
   * well-separated spectra: e == 0 on both sides, ||Y_gpu - Y_orc||_F / ||Y_orc||_F <= 1e-10 and,
     entry by entry, max |Y_gpu - Y_orc| <= 1e-10 max |Y_orc|;
   * every case: all entries finite and <= Omega, eq. (9) residual <= 1e-13;
-  * growth inputs: e > 0, eq. (9) by the oracle in long double, and the normalised solutions agree
-    to within ten times the oracle's own spread between two valid tile orders, or 1e-8 (these
-    inputs are ill-conditioned enough that rounding order alone moves the forward solution: at
-    m = n = 256 the spread is ~4e-4 and the GPU's difference ~4e-4; at the full 4096 size the
-    forward solution is not determined at all, see test_gpu_fullsize).
+  * growth inputs: e > 0, eq. (9) by the oracle in long double, the exponents of the largest
+    entries within one of each other plus the oracle's own exponent spread between two valid tile
+    orders, and the normalised solutions agree to within ten times the oracle's own spread, or
+    1e-8 (these inputs are ill-conditioned enough that rounding order alone moves the forward
+    solution: at m = n = 256 the spread is ~4e-4 and the GPU's difference ~4e-4; at 512 the
+    oracle's tile orders disagree by up to 5 binary orders in the largest entry; at the full 4096
+    size the forward solution is not determined at all, see test_gpu_fullsize).
 """
 import math
 import sys
@@ -123,7 +125,9 @@ def _growth_checks(orc, A, B, C, Y, e, Yo, eo, Yo2, eo2):
     ng, sg = normalised(Y)
     no, so = normalised(Yo)
     n2, s2 = normalised(Yo2)
-    assert abs((sg + e) - (so + eo)) <= 1
+    # the magnitude of the largest entry: one binary order, plus the oracle's own spread between
+    # its two tile orders (at m = n = 512 tile orders 128/64/32/16 give 10071/10070/10066/10071)
+    assert abs((sg + e) - (so + eo)) <= 1 + abs((s2 + eo2) - (so + eo))
     spread = rel(np.ldexp(n2, (s2 + eo2) - (so + eo)), no)
     err = rel(np.ldexp(ng, (sg + e) - (so + eo)), no)
     print(f"    growth: e_gpu={e} e_orc={eo} err={err:.2e} oracle spread={spread:.2e}")
