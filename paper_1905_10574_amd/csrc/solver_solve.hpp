@@ -730,10 +730,23 @@ __device__ double tile_norm_copy(const double *src, int64_t lsrc, const DevView 
     const int t = threadIdx.x, rr = t % mr, p = t / mr;
     double s = 0.0;
     if (p < g) {
-        for (int cc = p; cc < nc; cc += g) {
-            const double v = ldg(src + (int64_t)cc * lsrc + rr);
-            if (dst) st_dev(*dst, (int64_t)cc * ldst + rr, v);
-            s += fabs(v);
+        // eight columns' loads issued before their stores (a store may alias a later load, so
+        // one column at a time would cost a memory round trip each); the sum keeps column order
+        for (int c0 = p; c0 < nc; c0 += 8 * g) {
+            double v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int cc = c0 + j * g;
+                v[j] = cc < nc ? ldg(src + (int64_t)cc * lsrc + rr) : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int cc = c0 + j * g;
+                if (cc < nc) {
+                    if (dst) st_dev(*dst, (int64_t)cc * ldst + rr, v[j]);
+                    s += fabs(v[j]);
+                }
+            }
         }
     }
     part[t] = s;
